@@ -1,0 +1,163 @@
+/*
+ * fd6.h -- C ABI of the MI355X (gfx950) library for the per-substep kernel of
+ * a sixth-order finite-difference solver for isothermal compressible
+ * hydrodynamics (Pekkila, Vaisala, Kapyla, Kapyla, Anjum 2017, "Methods for
+ * compressible fluid simulation on GPUs using high-order finite differences").
+ *
+ * What one step computes (paper section / equation / algorithm):
+ *   state        lnrho, ux, uy, uz on an nx*ny*nz periodic grid with a ghost
+ *                zone of R = 3 cells (Sec. 2.3, Sec. 4)
+ *   right-hand   D lnrho/Dt = -div u                          eq. continuity
+ *   side         D u/Dt = -cs^2 grad lnrho + nu (lap u + (1/3) grad div u
+ *                         + 2 S . grad lnrho), f = 0          eq. navierstokes
+ *                S_ij = (d_j u_i + d_i u_j)/2 - (1/3) delta_ij div u  eq. tensor
+ *   derivatives  sixth-order central first, second and bidiagonal mixed
+ *                differences, eqs. first_derivatives, second_derivatives
+ *                (prefactor 1/(180 dx^2)), mixed_derivatives (Sec. 2.3); the
+ *                19-point variant forms grad div u as D1 of the divergence
+ *                field (eq. 19-point_mixed_derivatives, Sec. 4.2, Appendix A)
+ *   time step    2N-storage RK3, eq. 2N-RK_scheme (Sec. 2.4), substeps as in
+ *                Algorithm 2 (55 points) or Algorithm 3 (19 points), with the
+ *                Williamson coefficients alpha = (0, -5/9, -153/128),
+ *                beta = (1/3, 15/16, 8/15)
+ *
+ * Conventions for every entry point
+ *   - Return value: FD6_OK (0) or a negative fd6_status.  No C++ exception
+ *     crosses this boundary.  An argument error (FD6_EINVAL) leaves the
+ *     handle unchanged.  After FD6_EHIP, fd6_last_error() holds the HIP text.
+ *   - Host field arrays are compact FP64, nx*ny*nz values, C order [z][y][x]
+ *     (x fastest).  "_device" variants take device pointers with the same
+ *     layout; they are read or written on the handle's stream.
+ *   - Device memory: the caller allocates one workspace of
+ *     fd6_workspace_bytes() bytes, 256-byte aligned, and keeps it alive until
+ *     fd6_destroy().  The library borrows it and allocates no device memory.
+ *   - Streams: work is enqueued on the hipStream_t given at creation (or by
+ *     fd6_set_stream); NULL means the default stream.  fd6_rk3_step is
+ *     asynchronous; calls that return host data synchronise the stream.
+ *   - Handles are not thread-safe; distinct handles are independent.
+ */
+#ifndef FD6_H
+#define FD6_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FD6_ABI_VERSION 1
+
+typedef enum {
+    FD6_OK = 0,
+    FD6_EINVAL = -1,       /* bad argument (null pointer, size, parameter) */
+    FD6_ESTATE = -2,       /* step/get/reduce before set_params + init_fields */
+    FD6_ENOMEM = -3,       /* workspace smaller than fd6_workspace_bytes() */
+    FD6_EHIP = -4,         /* a HIP call failed; see fd6_last_error() */
+    FD6_ENONFINITE = -5,   /* fd6_reduce found NaN or Inf in the state */
+    FD6_EUNSUPPORTED = -6  /* valid but not implemented combination */
+} fd6_status;
+
+/* Storage and arithmetic precision of the state (Sec. 5 compares single and
+ * double precision).  FD6_FP32_ACC64 stores the state in FP32 and keeps the
+ * RK3 register w and the RK3 update arithmetic in FP64. */
+typedef enum { FD6_FP64 = 0, FD6_FP32 = 1, FD6_FP32_ACC64 = 2 } fd6_precision;
+
+/* Discretisation: 55-point single pass (Sec. 4.1, Algorithm 2) or 19-point
+ * two pass (Sec. 4.2, Algorithm 3). */
+typedef enum { FD6_55P = 0, FD6_19P = 1 } fd6_variant;
+
+typedef struct {
+    int32_t nx, ny, nz;  /* interior points, 6 <= n <= 4096 each */
+    int32_t precision;   /* fd6_precision */
+    int32_t variant;     /* fd6_variant */
+    int32_t flags;       /* reserved, must be 0 */
+} fd6_desc;
+
+/* Physical and numerical parameters: viscosity nu >= 0, sound speed cs >= 0,
+ * grid spacings dx, dy, dz > 0 (delta_i = L_i / N_i, Sec. 2.3), time step
+ * dt > 0.  All finite. */
+typedef struct {
+    double nu, cs, dx, dy, dz, dt;
+} fd6_params;
+
+/* FP64 global diagnostics of the state: mass = dV sum exp(lnrho), kinetic
+ * energy = dV sum exp(lnrho)|u|^2/2, sum of lnrho, max |u|, and the number
+ * of grid points holding a non-finite value in any field. */
+typedef struct {
+    double mass, kinetic_energy, sum_lnrho, umax;
+    int64_t nonfinite;
+} fd6_reductions;
+
+typedef struct fd6_box fd6_box;
+
+/* Library ABI version (FD6_ABI_VERSION). */
+int fd6_abi_version(void);
+
+/* Static text for a status code. */
+const char *fd6_status_string(int status);
+
+/* Device workspace needed by a box described by desc. */
+int fd6_workspace_bytes(const fd6_desc *desc, size_t *bytes);
+
+/* Create a box in the caller's workspace.  d_workspace: device pointer,
+ * 256-byte aligned, at least fd6_workspace_bytes() bytes; stream: a
+ * hipStream_t or NULL.  On success *out owns no device memory of its own. */
+int fd6_create(const fd6_desc *desc, void *d_workspace, size_t bytes, void *stream,
+               fd6_box **out);
+
+/* Release the handle (the workspace stays the caller's). NULL is accepted. */
+int fd6_destroy(fd6_box *box);
+
+/* Replace the stream used by subsequent calls. */
+int fd6_set_stream(fd6_box *box, void *stream);
+
+/* Set nu, cs, dx, dy, dz, dt (validated as described above). */
+int fd6_set_params(fd6_box *box, const fd6_params *params);
+
+/* Load the state from host FP64 arrays (converted to the storage precision
+ * with round-to-nearest-even); resets the RK3 register. Synchronises. */
+int fd6_init_fields(fd6_box *box, const double *lnrho, const double *ux, const double *uy,
+                    const double *uz);
+
+/* Same from device FP64 arrays; asynchronous on the box's stream. */
+int fd6_init_fields_device(fd6_box *box, const double *lnrho, const double *ux,
+                           const double *uy, const double *uz);
+
+/* Advance nsteps >= 0 full RK3 steps (3 substeps each: periodic ghost fill,
+ * then the fused right-hand side + 2N-RK3 update, Algorithm 2; or the two
+ * passes of Algorithm 3).  Asynchronous on the box's stream. */
+int fd6_rk3_step(fd6_box *box, int32_t nsteps);
+
+/* Copy the state to host FP64 arrays.  Synchronises. */
+int fd6_get_fields(fd6_box *box, double *lnrho, double *ux, double *uy, double *uz);
+
+/* Copy the state to device FP64 arrays.  Asynchronous. */
+int fd6_get_fields_device(fd6_box *box, double *lnrho, double *ux, double *uy, double *uz);
+
+/* FP64 diagnostics of the current state, deterministic (fixed reduction
+ * order).  Synchronises.  Returns FD6_ENONFINITE (with *out filled) when
+ * out->nonfinite > 0. */
+int fd6_reduce(fd6_box *box, fd6_reductions *out);
+
+/* Right-hand side d/dt (lnrho, ux, uy, uz) of the current state, evaluated by
+ * the same kernels as a substep (precision of the box), to host FP64 arrays.
+ * Overwrites the RK3 register, which holds no state between full steps
+ * because alpha(1) = 0.  Synchronises. */
+int fd6_rhs(fd6_box *box, double *r_lnrho, double *r_ux, double *r_uy, double *r_uz);
+
+/* Kernel shape of the 55-point substep: 0 = one thread per point with every
+ * tap read through the caches; 1 .. fd6_tile_count()-1 = z-sweep kernels
+ * with different xy tile shapes.  Results are identical up to rounding
+ * order; the choice only changes speed (see the autotuner). */
+int fd6_tile_count(void);
+int fd6_set_tile(fd6_box *box, int32_t tile);
+
+/* Text of the last error on this handle ("" if none). */
+const char *fd6_last_error(const fd6_box *box);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD6_H */

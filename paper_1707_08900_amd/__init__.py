@@ -1,0 +1,220 @@
+"""MI355X (gfx950) per-substep kernel of a sixth-order finite-difference solver
+for isothermal compressible hydrodynamics (Pekkila et al. 2017).
+
+This module is a thin ctypes binding over ``libfd6.so`` (C ABI declared in
+``include/fd6.h``): argument marshalling only.  Every step of the computation
+runs in the library's HIP kernels; PyTorch provides the device workspace and
+the HIP stream.  There is no CPU fallback: without the built library the
+import fails, and without a GPU creating a box fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # loaded first: its HIP runtime is the one the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfd6.so")
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_acc64": 2}
+VARIANTS = {"55p": 0, "19p": 1}
+STATUS = {0: "FD6_OK", -1: "FD6_EINVAL", -2: "FD6_ESTATE", -3: "FD6_ENOMEM", -4: "FD6_EHIP",
+          -5: "FD6_ENONFINITE", -6: "FD6_EUNSUPPORTED"}
+
+# every symbol the header declares
+ABI_SYMBOLS = (
+    "fd6_abi_version", "fd6_status_string", "fd6_workspace_bytes", "fd6_create", "fd6_destroy",
+    "fd6_set_stream", "fd6_set_params", "fd6_init_fields", "fd6_init_fields_device",
+    "fd6_rk3_step", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
+    "fd6_tile_count", "fd6_set_tile", "fd6_last_error",
+)
+
+
+class Fd6Desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class Fd6Params(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("nu", "cs", "dx", "dy", "dz", "dt")]
+
+
+class Fd6Reductions(ctypes.Structure):
+    _fields_ = [("mass", ctypes.c_double), ("kinetic_energy", ctypes.c_double),
+                ("sum_lnrho", ctypes.c_double), ("umax", ctypes.c_double),
+                ("nonfinite", ctypes.c_int64)]
+
+
+class Fd6Error(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str = ""):
+        self.status = status
+        msg = f"{what}: {STATUS.get(status, status)}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+def _declare(lib):
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "fd6_abi_version": (I, []),
+        "fd6_status_string": (ctypes.c_char_p, [I]),
+        "fd6_workspace_bytes": (I, [ctypes.POINTER(Fd6Desc), ctypes.POINTER(ctypes.c_size_t)]),
+        "fd6_create": (I, [ctypes.POINTER(Fd6Desc), P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
+        "fd6_destroy": (I, [P]),
+        "fd6_set_stream": (I, [P, P]),
+        "fd6_set_params": (I, [P, ctypes.POINTER(Fd6Params)]),
+        "fd6_init_fields": (I, [P, D, D, D, D]),
+        "fd6_init_fields_device": (I, [P, P, P, P, P]),
+        "fd6_rk3_step": (I, [P, ctypes.c_int32]),
+        "fd6_get_fields": (I, [P, D, D, D, D]),
+        "fd6_get_fields_device": (I, [P, P, P, P, P]),
+        "fd6_reduce": (I, [P, ctypes.POINTER(Fd6Reductions)]),
+        "fd6_rhs": (I, [P, D, D, D, D]),
+        "fd6_tile_count": (I, []),
+        "fd6_set_tile": (I, [P, ctypes.c_int32]),
+        "fd6_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def library():
+    """Load libfd6.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1707_08900_amd.build`")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def workspace_bytes(shape, precision="fp32", variant="55p") -> int:
+    nz, ny, nx = shape
+    d = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS[variant], 0)
+    out = ctypes.c_size_t()
+    rc = library().fd6_workspace_bytes(ctypes.byref(d), ctypes.byref(out))
+    if rc != 0:
+        raise Fd6Error(rc, "fd6_workspace_bytes")
+    return out.value
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Box:
+    """One periodic box: lnrho, ux, uy, uz of shape (nz, ny, nx) on the GPU."""
+
+    def __init__(self, shape: Sequence[int], precision: str = "fp32", variant: str = "55p",
+                 device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1707_08900_amd needs a ROCm GPU (gfx950); none is visible")
+        self.lib = library()
+        self.shape = tuple(int(s) for s in shape)
+        self.precision, self.variant = precision, variant
+        self.device = torch.device(device)
+        nz, ny, nx = self.shape
+        self.desc = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS[variant], 0)
+        nbytes = workspace_bytes(self.shape, precision, variant)
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.fd6_create(ctypes.byref(self.desc), ctypes.c_void_p(aligned),
+                                        nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(h)), "fd6_create", handle=False)
+        self.h = h
+        self.params = None
+
+    # -- helpers --------------------------------------------------------
+    def _check(self, rc, what, handle=True):
+        if rc != 0:
+            detail = ""
+            if handle and getattr(self, "h", None):
+                detail = (self.lib.fd6_last_error(self.h) or b"").decode()
+            raise Fd6Error(rc, what, detail)
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fd6_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API --------------------------------------------------------------
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        self._check(self.lib.fd6_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)),
+                    "fd6_set_stream")
+
+    def set_params(self, nu, cs, dx, dy, dz, dt):
+        self.params = Fd6Params(nu, cs, dx, dy, dz, dt)
+        self._check(self.lib.fd6_set_params(self.h, ctypes.byref(self.params)), "fd6_set_params")
+
+    def init_fields(self, fields):
+        """fields: four float64 arrays (numpy on the host, or torch on this device)."""
+        if all(isinstance(f, torch.Tensor) and f.is_cuda for f in fields):
+            ts = [f.contiguous() for f in fields]
+            for t in ts:
+                assert t.dtype == torch.float64 and tuple(t.shape) == self.shape
+            self._keep = ts
+            self._check(self.lib.fd6_init_fields_device(
+                self.h, *[ctypes.c_void_p(t.data_ptr()) for t in ts]), "fd6_init_fields_device")
+            return
+        arrs = [np.ascontiguousarray(f, dtype=np.float64) for f in fields]
+        for a in arrs:
+            assert a.shape == self.shape, (a.shape, self.shape)
+        self._check(self.lib.fd6_init_fields(self.h, *[_dptr(a) for a in arrs]),
+                    "fd6_init_fields")
+
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.fd6_rk3_step(self.h, int(nsteps)), "fd6_rk3_step")
+
+    def get_fields(self):
+        out = [np.empty(self.shape) for _ in range(4)]
+        self._check(self.lib.fd6_get_fields(self.h, *[_dptr(a) for a in out]), "fd6_get_fields")
+        return out
+
+    def get_fields_device(self):
+        out = [torch.empty(self.shape, dtype=torch.float64, device=self.device) for _ in range(4)]
+        self._check(self.lib.fd6_get_fields_device(
+            self.h, *[ctypes.c_void_p(t.data_ptr()) for t in out]), "fd6_get_fields_device")
+        return out
+
+    def rhs(self):
+        out = [np.empty(self.shape) for _ in range(4)]
+        self._check(self.lib.fd6_rhs(self.h, *[_dptr(a) for a in out]), "fd6_rhs")
+        return out
+
+    def reduce(self, allow_nonfinite: bool = False):
+        r = Fd6Reductions()
+        rc = self.lib.fd6_reduce(self.h, ctypes.byref(r))
+        if rc != 0 and not (allow_nonfinite and rc == -5):
+            self._check(rc, "fd6_reduce")
+        return {"mass": r.mass, "kinetic_energy": r.kinetic_energy, "sum_lnrho": r.sum_lnrho,
+                "umax": r.umax, "nonfinite": int(r.nonfinite)}
+
+    def set_tile(self, tile: int):
+        self._check(self.lib.fd6_set_tile(self.h, int(tile)), "fd6_set_tile")
+
+
+def tile_count() -> int:
+    return library().fd6_tile_count()

@@ -1,0 +1,553 @@
+// Host runtime and C ABI of the fd6 library (declared in include/fd6.h).
+//
+// A box borrows one caller-allocated device workspace and carves it into:
+// two sets of four ghosted state fields (in / out of a substep, swapped by
+// pointer as in Algorithm 2), the four RK3 register fields w, the divergence
+// field of the 19-point method, reduction partials, and an FP64 staging area
+// for host transfers.  No device memory is allocated by the library.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "../../include/fd6.h"
+#include "fd6_internal.hpp"
+
+using namespace fd6;
+
+struct fd6_box {
+    fd6_desc desc{};
+    Geom geom{};
+    fd6_params params{};
+    bool have_params = false;
+    bool have_fields = false;
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t tsize = 0;   // bytes per state element
+    size_t wsize = 0;   // bytes per w element
+    void* state[2][4] = {};
+    void* w[4] = {};
+    void* div = nullptr;
+    double* partials = nullptr;
+    double* result = nullptr;
+    double* staging = nullptr;
+    long long staging_elems = 0;
+    int cur = 0;
+    int tile = 1;
+    std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr long long kMaxFieldElems = (1LL << 31) - 1;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+    Geom g;
+    size_t tsize, wsize;
+    size_t off_state[2][4], off_w[4], off_div, off_partials, off_result, off_staging, total;
+    long long staging_elems;
+};
+
+int precision_sizes(int prec, size_t* ts, size_t* wsz) {
+    switch (prec) {
+    case FD6_FP64: *ts = 8; *wsz = 8; return 0;
+    case FD6_FP32: *ts = 4; *wsz = 4; return 0;
+    case FD6_FP32_ACC64: *ts = 4; *wsz = 8; return 0;
+    default: return -1;
+    }
+}
+
+int validate_desc(const fd6_desc* d) {
+    if (!d) return FD6_EINVAL;
+    if (d->nx < 2 * kR || d->ny < 2 * kR || d->nz < 2 * kR) return FD6_EINVAL;
+    if (d->nx > 4096 || d->ny > 4096 || d->nz > 4096) return FD6_EINVAL;
+    if (d->flags != 0) return FD6_EINVAL;
+    if (d->variant != FD6_55P && d->variant != FD6_19P) return FD6_EINVAL;
+    size_t a, b;
+    if (precision_sizes(d->precision, &a, &b)) return FD6_EINVAL;
+    return FD6_OK;
+}
+
+int make_plan(const fd6_desc* d, Plan* p) {
+    int rc = validate_desc(d);
+    if (rc) return rc;
+    precision_sizes(d->precision, &p->tsize, &p->wsize);
+    Geom& g = p->g;
+    g.nx = d->nx;
+    g.ny = d->ny;
+    g.nz = d->nz;
+    const long long A = 128 / (long long)p->tsize;  // elements per 128-byte line
+    g.px = (int)round_up((size_t)(A + d->nx + kR), (size_t)A);
+    g.plane = (long long)g.px * (d->ny + 2 * kR);
+    g.origin = kR * g.plane + kR * (long long)g.px + A;
+    const long long fe = g.plane * (d->nz + 2 * kR);
+    g.felems = (long long)round_up((size_t)fe * p->tsize, kAlign) / (long long)p->tsize;
+    const long long AW = 128 / (long long)p->wsize;
+    g.wpx = (int)round_up((size_t)d->nx, (size_t)AW);
+    g.wplane = (long long)g.wpx * d->ny;
+    g.wfelems = (long long)round_up((size_t)(g.wplane * d->nz) * p->wsize, kAlign) /
+                (long long)p->wsize;
+    if (g.felems > kMaxFieldElems || g.wfelems > kMaxFieldElems) return FD6_EUNSUPPORTED;
+    size_t off = 0;
+    const size_t fbytes = (size_t)g.felems * p->tsize;
+    for (int s = 0; s < 2; ++s)
+        for (int q = 0; q < 4; ++q) {
+            p->off_state[s][q] = off;
+            off += fbytes;
+        }
+    for (int q = 0; q < 4; ++q) {
+        p->off_w[q] = off;
+        off += (size_t)g.wfelems * p->wsize;
+    }
+    p->off_div = off;
+    if (d->variant == FD6_19P) off += fbytes;
+    p->off_partials = off;
+    off += round_up((size_t)kReduceBlocks * kReduceSlots * sizeof(double), kAlign);
+    p->off_result = off;
+    off += kAlign;
+    const long long plane_c = (long long)d->nx * d->ny;
+    long long st = (long long)d->nx * d->ny * d->nz;
+    const long long cap = 1LL << 22;  // 32 MiB of FP64, at least one plane
+    if (st > cap) st = (cap / plane_c) * plane_c;
+    if (st < plane_c) st = plane_c;
+    p->staging_elems = st;
+    p->off_staging = off;
+    off += round_up((size_t)st * sizeof(double), kAlign);
+    p->total = off;
+    return FD6_OK;
+}
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int hip_fail(fd6_box* b, hipError_t e, const char* what) {
+    b->err = std::string(what) + ": " + hipGetErrorString(e);
+    return FD6_EHIP;
+}
+
+#define HIPCHK(b, expr)                                      \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail((b), e_, #expr); \
+    } while (0)
+
+// RK3 coefficients of the 2N-storage scheme (Williamson 1980), alpha(1) = 0.
+constexpr double kAlpha[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+constexpr double kBeta[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+template <typename T>
+Coef<T> make_coef(const fd6_params& p) {
+    const double h[3] = {p.dx, p.dy, p.dz};
+    const double w1[3] = {45.0, -9.0, 1.0};
+    const double w2[4] = {-490.0, 270.0, -27.0, 2.0};
+    const double wm[3] = {270.0, -27.0, 2.0};
+    Coef<T> c{};
+    double d2[3][4];
+    for (int a = 0; a < 3; ++a) {
+        for (int k = 0; k < 3; ++k) c.d1[a][k] = T(w1[k] / (60.0 * h[a]));
+        for (int k = 0; k < 4; ++k) {
+            d2[a][k] = w2[k] / (180.0 * h[a] * h[a]);
+            c.d2[a][k] = T(d2[a][k]);
+            c.lp[a][k] = T(p.nu * d2[a][k]);
+        }
+    }
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};  // xy, xz, yz
+    for (int q = 0; q < 3; ++q)
+        for (int k = 0; k < 3; ++k) {
+            const double m = wm[k] / (720.0 * h[pa[q]] * h[pb[q]]);
+            c.mx[q][k] = T(m);
+            c.mw[q][k] = T(p.nu * m / 3.0);
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < 4; ++k)
+                c.lw[i][a][k] = T(p.nu * (a == i ? 4.0 / 3.0 : 1.0) * d2[a][k]);
+    c.nu = T(p.nu);
+    c.cs2 = T(p.cs * p.cs);
+    c.nu3 = p.nu / 3.0;
+    double sg[3], sg4[3];
+    for (int a = 0; a < 3; ++a) {
+        sg[a] = p.nu / (180.0 * h[a] * h[a]);
+        sg4[a] = (4.0 / 3.0) * sg[a];
+        c.sg[a] = T(sg[a]);
+        c.sg4[a] = T(sg4[a]);
+    }
+    for (int i = 0; i < 3; ++i) {
+        const double sx = i == 0 ? sg4[0] : sg[0], sy = i == 1 ? sg4[1] : sg[1];
+        c.kxy[i] = T(-490.0 * (sx + sy));
+    }
+    for (int q = 0; q < 3; ++q) c.mu[q] = T(p.nu / (3.0 * 720.0 * h[pa[q]] * h[pb[q]]));
+    return c;
+}
+
+template <typename T>
+Fields4<T> fields_of(void* const f[4]) {
+    Fields4<T> r;
+    for (int q = 0; q < 4; ++q) r.f[q] = static_cast<T*>(f[q]);
+    return r;
+}
+
+template <typename T, typename TW>
+int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk) {
+    const Geom& g = b->geom;
+    Fields4<T> in = fields_of<T>(b->state[b->cur]);
+    Fields4<T> out = fields_of<T>(b->state[b->cur ^ 1]);
+    Fields4<TW> w = fields_of<TW>(b->w);
+    const Coef<T> c = make_coef<T>(b->params);
+    HIPCHK(b, launch_ghost_fill<T>(g, in, 4, b->stream));
+    if (b->desc.variant == FD6_55P) {
+        HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->stream)));
+    } else {
+        T* dv = static_cast<T*>(b->div);
+        HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->stream)));
+        Fields4<T> d1{{dv, dv, dv, dv}};
+        HIPCHK(b, launch_ghost_fill<T>(g, d1, 1, b->stream));
+        HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, b->stream)));
+    }
+    b->cur ^= 1;
+    return FD6_OK;
+}
+
+template <typename T, typename TW>
+int do_steps(fd6_box* b, int nsteps) {
+    const double dt = b->params.dt;
+    for (int n = 0; n < nsteps; ++n)
+        for (int s = 0; s < 3; ++s) {
+            RKCoef<TW> rk{TW(kAlpha[s]), TW(kBeta[s]), TW(dt)};
+            int rc = do_substep<T, TW>(b, s + 1, rk);
+            if (rc) return rc;
+        }
+    return FD6_OK;
+}
+
+template <typename T, typename TW>
+int do_rhs(fd6_box* b, double* const out[4]) {
+    // substep-1 arithmetic with dt = 1 leaves w = r; the result state is
+    // discarded by not swapping back
+    RKCoef<TW> rk{TW(0), TW(0), TW(1)};
+    int rc = do_substep<T, TW>(b, 1, rk);
+    b->cur ^= 1;  // keep the original state current
+    if (rc) return rc;
+    const Geom& g = b->geom;
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    for (int q = 0; q < 4; ++q) {
+        // export in chunks that fit the staging area
+        const long long plane_c = (long long)g.nx * g.ny;
+        if (b->staging_elems >= n) {
+            HIPCHK(b, launch_export_w<TW>(g, static_cast<TW*>(b->w[q]), b->staging, b->stream));
+            HIPCHK(b, hipMemcpyAsync(out[q], b->staging, n * sizeof(double),
+                                     hipMemcpyDeviceToHost, b->stream));
+            HIPCHK(b, hipStreamSynchronize(b->stream));
+        } else {
+            (void)plane_c;
+            b->err = "fd6_rhs: box too large for the staging area";
+            return FD6_EUNSUPPORTED;
+        }
+    }
+    return FD6_OK;
+}
+
+template <typename T>
+int import_host(fd6_box* b, const double* const src[4]) {
+    const Geom& g = b->geom;
+    const long long plane_c = (long long)g.nx * g.ny;
+    const int chunk = (int)(b->staging_elems / plane_c);
+    for (int q = 0; q < 4; ++q) {
+        T* dst = static_cast<T*>(b->state[b->cur][q]);
+        for (int z = 0; z < g.nz; z += chunk) {
+            const int np = (z + chunk <= g.nz) ? chunk : g.nz - z;
+            HIPCHK(b, hipMemcpyAsync(b->staging, src[q] + (long long)z * plane_c,
+                                     (size_t)np * plane_c * sizeof(double), hipMemcpyHostToDevice,
+                                     b->stream));
+            HIPCHK(b, launch_import<T>(g, b->staging, dst, z, np, b->stream));
+            HIPCHK(b, hipStreamSynchronize(b->stream));
+        }
+    }
+    return FD6_OK;
+}
+
+template <typename T>
+int export_host(fd6_box* b, double* const dst[4]) {
+    const Geom& g = b->geom;
+    const long long plane_c = (long long)g.nx * g.ny;
+    const int chunk = (int)(b->staging_elems / plane_c);
+    for (int q = 0; q < 4; ++q) {
+        const T* src = static_cast<const T*>(b->state[b->cur][q]);
+        for (int z = 0; z < g.nz; z += chunk) {
+            const int np = (z + chunk <= g.nz) ? chunk : g.nz - z;
+            HIPCHK(b, launch_export<T>(g, src, b->staging, z, np, b->stream));
+            HIPCHK(b, hipMemcpyAsync(dst[q] + (long long)z * plane_c, b->staging,
+                                     (size_t)np * plane_c * sizeof(double), hipMemcpyDeviceToHost,
+                                     b->stream));
+            HIPCHK(b, hipStreamSynchronize(b->stream));
+        }
+    }
+    return FD6_OK;
+}
+
+template <typename T>
+int import_device(fd6_box* b, const double* const src[4]) {
+    for (int q = 0; q < 4; ++q)
+        HIPCHK(b, launch_import<T>(b->geom, src[q], static_cast<T*>(b->state[b->cur][q]), 0,
+                                   b->geom.nz, b->stream));
+    return FD6_OK;
+}
+
+template <typename T>
+int export_device(fd6_box* b, double* const dst[4]) {
+    for (int q = 0; q < 4; ++q)
+        HIPCHK(b, launch_export<T>(b->geom, static_cast<const T*>(b->state[b->cur][q]), dst[q], 0,
+                                   b->geom.nz, b->stream));
+    return FD6_OK;
+}
+
+int reset_w(fd6_box* b) {
+    if (b->wsize == 8)
+        HIPCHK(b, launch_zero_w<double>(b->geom, fields_of<double>(b->w), b->stream));
+    else
+        HIPCHK(b, launch_zero_w<float>(b->geom, fields_of<float>(b->w), b->stream));
+    return FD6_OK;
+}
+
+template <typename T>
+int do_reduce(fd6_box* b, fd6_reductions* out) {
+    const Geom& g = b->geom;
+    const double dV = b->params.dx * b->params.dy * b->params.dz;
+    HIPCHK(b, launch_reduce<T>(g, fields_of<T>(b->state[b->cur]), b->partials, b->result, dV,
+                               b->stream));
+    double r[kReduceSlots];
+    HIPCHK(b, hipMemcpyAsync(r, b->result, 5 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    out->mass = r[0];
+    out->kinetic_energy = r[1];
+    out->sum_lnrho = r[2];
+    out->umax = r[3];
+    out->nonfinite = (int64_t)r[4];
+    return out->nonfinite > 0 ? FD6_ENONFINITE : FD6_OK;
+}
+
+// Precision dispatch: FP64 -> (double, double); FP32 -> (float, float);
+// FP32 state with FP64 RK3 register -> (float, double).
+template <typename F>
+int dispatch(fd6_box* b, F&& f) {
+    switch (b->desc.precision) {
+    case FD6_FP64: return f((double*)nullptr, (double*)nullptr);
+    case FD6_FP32: return f((float*)nullptr, (float*)nullptr);
+    default: return f((float*)nullptr, (double*)nullptr);
+    }
+}
+
+template <typename F>
+int guarded(fd6_box* b, F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        if (b) b->err = "host allocation failed";
+        return FD6_ENOMEM;
+    } catch (const std::exception& e) {
+        if (b) b->err = e.what();
+        return FD6_EHIP;
+    } catch (...) {
+        if (b) b->err = "unknown exception";
+        return FD6_EHIP;
+    }
+}
+
+bool ready(fd6_box* b) { return b->have_params && b->have_fields; }
+
+}  // namespace
+
+extern "C" {
+
+int fd6_abi_version(void) { return FD6_ABI_VERSION; }
+
+const char* fd6_status_string(int s) {
+    switch (s) {
+    case FD6_OK: return "ok";
+    case FD6_EINVAL: return "invalid argument";
+    case FD6_ESTATE: return "invalid state (set params and init fields first)";
+    case FD6_ENOMEM: return "workspace too small";
+    case FD6_EHIP: return "HIP error";
+    case FD6_ENONFINITE: return "non-finite values in the state";
+    case FD6_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+int fd6_workspace_bytes(const fd6_desc* desc, size_t* bytes) {
+    if (!bytes) return FD6_EINVAL;
+    Plan p;
+    int rc = make_plan(desc, &p);
+    if (rc) return rc;
+    *bytes = p.total;
+    return FD6_OK;
+}
+
+int fd6_create(const fd6_desc* desc, void* d_ws, size_t bytes, void* stream, fd6_box** out) {
+    if (!out || !d_ws) return FD6_EINVAL;
+    Plan p;
+    int rc = make_plan(desc, &p);
+    if (rc) return rc;
+    if (((uintptr_t)d_ws) % kAlign != 0) return FD6_EINVAL;
+    if (bytes < p.total) return FD6_ENOMEM;
+    return guarded(nullptr, [&]() -> int {
+        fd6_box* b = new fd6_box();
+        b->desc = *desc;
+        b->geom = p.g;
+        b->stream = static_cast<hipStream_t>(stream);
+        b->ws = static_cast<char*>(d_ws);
+        b->ws_bytes = bytes;
+        b->tsize = p.tsize;
+        b->wsize = p.wsize;
+        for (int s = 0; s < 2; ++s)
+            for (int q = 0; q < 4; ++q) b->state[s][q] = b->ws + p.off_state[s][q];
+        for (int q = 0; q < 4; ++q) b->w[q] = b->ws + p.off_w[q];
+        b->div = b->ws + p.off_div;
+        b->partials = reinterpret_cast<double*>(b->ws + p.off_partials);
+        b->result = reinterpret_cast<double*>(b->ws + p.off_result);
+        b->staging = reinterpret_cast<double*>(b->ws + p.off_staging);
+        b->staging_elems = p.staging_elems;
+        *out = b;
+        return FD6_OK;
+    });
+}
+
+int fd6_destroy(fd6_box* b) {
+    delete b;
+    return FD6_OK;
+}
+
+int fd6_set_stream(fd6_box* b, void* stream) {
+    if (!b) return FD6_EINVAL;
+    b->stream = static_cast<hipStream_t>(stream);
+    return FD6_OK;
+}
+
+int fd6_set_params(fd6_box* b, const fd6_params* p) {
+    if (!b || !p) return FD6_EINVAL;
+    if (!finite_nonneg(p->nu) || !finite_nonneg(p->cs) || !finite_pos(p->dx) ||
+        !finite_pos(p->dy) || !finite_pos(p->dz) || !finite_pos(p->dt))
+        return FD6_EINVAL;
+    b->params = *p;
+    b->have_params = true;
+    return FD6_OK;
+}
+
+int fd6_init_fields(fd6_box* b, const double* lnrho, const double* ux, const double* uy,
+                    const double* uz) {
+    if (!b || !lnrho || !ux || !uy || !uz) return FD6_EINVAL;
+    return guarded(b, [&]() -> int {
+        const double* src[4] = {lnrho, ux, uy, uz};
+        b->cur = 0;
+        int rc = dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return import_host<T>(b, src);
+        });
+        if (rc) return rc;
+        rc = reset_w(b);
+        if (rc) return rc;
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+        b->have_fields = true;
+        return FD6_OK;
+    });
+}
+
+int fd6_init_fields_device(fd6_box* b, const double* lnrho, const double* ux, const double* uy,
+                           const double* uz) {
+    if (!b || !lnrho || !ux || !uy || !uz) return FD6_EINVAL;
+    return guarded(b, [&]() -> int {
+        const double* src[4] = {lnrho, ux, uy, uz};
+        b->cur = 0;
+        int rc = dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return import_device<T>(b, src);
+        });
+        if (rc) return rc;
+        rc = reset_w(b);
+        if (rc) return rc;
+        b->have_fields = true;
+        return FD6_OK;
+    });
+}
+
+int fd6_rk3_step(fd6_box* b, int32_t nsteps) {
+    if (!b || nsteps < 0) return FD6_EINVAL;
+    if (!ready(b)) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        return dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            return do_steps<T, TW>(b, nsteps);
+        });
+    });
+}
+
+int fd6_get_fields(fd6_box* b, double* lnrho, double* ux, double* uy, double* uz) {
+    if (!b || !lnrho || !ux || !uy || !uz) return FD6_EINVAL;
+    if (!b->have_fields) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        double* dst[4] = {lnrho, ux, uy, uz};
+        return dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return export_host<T>(b, dst);
+        });
+    });
+}
+
+int fd6_get_fields_device(fd6_box* b, double* lnrho, double* ux, double* uy, double* uz) {
+    if (!b || !lnrho || !ux || !uy || !uz) return FD6_EINVAL;
+    if (!b->have_fields) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        double* dst[4] = {lnrho, ux, uy, uz};
+        return dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return export_device<T>(b, dst);
+        });
+    });
+}
+
+int fd6_reduce(fd6_box* b, fd6_reductions* out) {
+    if (!b || !out) return FD6_EINVAL;
+    if (!ready(b)) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        return dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return do_reduce<T>(b, out);
+        });
+    });
+}
+
+int fd6_rhs(fd6_box* b, double* r0, double* r1, double* r2, double* r3) {
+    if (!b || !r0 || !r1 || !r2 || !r3) return FD6_EINVAL;
+    if (!ready(b)) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        double* out[4] = {r0, r1, r2, r3};
+        return dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            return do_rhs<T, TW>(b, out);
+        });
+    });
+}
+
+const char* fd6_last_error(const fd6_box* b) { return b ? b->err.c_str() : ""; }
+
+// Kernel selection for the 55-point substep (tuning hook; 0 = direct
+// one-thread-per-point kernel, 1.. = z-sweep tile shapes).
+int fd6_set_tile(fd6_box* b, int32_t tile) {
+    if (!b || tile < 0 || tile >= substep55_tile_count()) return FD6_EINVAL;
+    b->tile = tile;
+    return FD6_OK;
+}
+
+int fd6_tile_count(void) { return substep55_tile_count(); }
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal definitions shared by the HIP kernels and the host runtime of the
+// fd6 library (sixth-order finite-difference RK3 substep for isothermal
+// compressible hydrodynamics, Pekkila et al. 2017).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fd6 {
+
+constexpr int kR = 3;  // stencil radius: sixth order, n = 2R (Sec. 2.3)
+
+// Storage geometry of one box.
+//
+// A state field is a ghosted array: interior (i, j, k), 0 <= i < nx, lives at
+// element  origin + k * plane + j * px + i,  for -3 <= i < nx + 3 likewise.
+// Rows are padded so that every row starts on a 128-byte boundary and the
+// interior point i = 0 of every row is 128-byte aligned (the ghost cells
+// i = -3..-1 sit at the end of the preceding 128-byte line).
+//
+// The RK3 register w has no ghost zone: (i, j, k) lives at
+// k * wplane + j * wpx + i, rows 128-byte aligned.
+struct Geom {
+    int nx, ny, nz;
+    int px;                // elements per state row
+    long long plane;       // elements per state plane = px * (ny + 6)
+    long long origin;      // element of interior (0, 0, 0)
+    long long felems;      // elements per state field (multiple of 256 B)
+    int wpx;               // elements per w row
+    long long wplane;      // wpx * ny
+    long long wfelems;     // elements per w field (multiple of 256 B)
+};
+
+// Four state fields (lnrho, ux, uy, uz) and four w fields.
+template <typename T>
+struct Fields4 {
+    T* f[4];
+};
+
+// RK3 substep constants (eq. 2N-RK_scheme): w <- alpha w + dt r,
+// out <- in + beta w.
+template <typename TW>
+struct RKCoef {
+    TW alpha, beta, dt;
+};
+
+// Finite-difference weights with the grid spacings folded in (Sec. 2.3).
+//   d1[a][k-1]  = {45, -9, 1}[k-1] / (60 h_a)          first derivative
+//   d2[a][k]    = {-490, 270, -27, 2}[k] / (180 h_a^2)  second derivative
+//   mx[p][k-1]  = {270, -27, 2}[k-1] / (720 h_a h_b)    mixed, p = xy, xz, yz
+// The fused kernel also uses combinations of these; the host precomputes
+// them in FP64 and rounds once to the working precision.
+template <typename T>
+struct Coef {
+    T d1[3][3];
+    T d2[3][4];
+    T mx[3][3];
+    T nu, cs2;
+    // Linear viscous part of the momentum equation for component i:
+    //   L_i = lap u_i + (1/3) d_i div u
+    //       = sum_a (1 + delta_ia / 3) D2_a u_i + (1/3) sum_{j != i} D_ij u_j
+    // lw[i][a][k]: weight of the second-derivative tap k along axis a in L_i
+    // (nu folded in), mw[p][k-1]: mixed weights / 3 (nu folded in).
+    T lw[3][3][4];
+    T mw[3][3];
+    // 19-point method: nu-scaled plain second-derivative weights (nu lap u)
+    // and nu / 3 in FP64 for the pass-2 factor dt (nu / 3).
+    T lp[3][4];
+    double nu3;
+    // Scale factors for stencils written with their integer weights
+    // (second derivative 2, -27, 270, -490; mixed 270, -27, 2):
+    //   sg[a]  = nu / (180 h_a^2),  sg4[a] = (4/3) sg[a]
+    //   kxy[i] = -490 (s_ix + s_iy), s_ia = (a == i ? sg4 : sg)[a]
+    //   mu[p]  = nu / (3 * 720 h_a h_b), p = xy, xz, yz
+    T sg[3], sg4[3], kxy[3], mu[3];
+};
+
+// Host-side launchers (implemented in the .hip files).
+template <typename T>
+hipError_t launch_ghost_fill(const Geom& g, Fields4<T> f, int nfields, hipStream_t s);
+
+template <typename T>
+hipError_t launch_import(const Geom& g, const double* src, T* dst, long long zbeg, int nplanes,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_export(const Geom& g, const T* src, double* dst, long long zbeg, int nplanes,
+                         hipStream_t s);
+template <typename TW>
+hipError_t launch_export_w(const Geom& g, const TW* src, double* dst, hipStream_t s);
+template <typename TW>
+hipError_t launch_zero_w(const Geom& g, Fields4<TW> w, hipStream_t s);
+
+// 55-point fused right-hand side + RK3 update for substep s (1, 2, 3).
+template <typename T, typename TW>
+hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                            hipStream_t st);
+
+// 19-point method: pass 1 (divergence, partial update) and pass 2.
+template <typename T, typename TW>
+hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, hipStream_t st);
+template <typename T, typename TW>
+hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
+                          const Coef<T>& c, const RKCoef<TW>& rk, hipStream_t st);
+
+// FP64 reductions: per-block partials then one fixed-order final block.
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceSlots = 8;  // mass, ke, sum lnrho, umax, nonfinite, pad
+template <typename T>
+hipError_t launch_reduce(const Geom& g, Fields4<T> f, double* partials, double* result,
+                         double dV, hipStream_t s);
+
+int substep55_tile_count();
+
+}  // namespace fd6

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/fd6.h declares, and its validation layer rejects
+bad arguments and out-of-order calls without touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fd6.h")
+
+
+def header_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fd6_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_1707_08900_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        pytest.fail("libfd6.so is not built (python -m paper_1707_08900_amd.build)")
+    return p
+
+
+def test_exports_every_declared_symbol(pkg):
+    lib = pkg.library()
+    declared = header_symbols()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(pkg.ABI_SYMBOLS)
+
+
+def test_version_and_status_strings(pkg):
+    lib = pkg.library()
+    assert lib.fd6_abi_version() == 1
+    for s in range(-6, 1):
+        assert lib.fd6_status_string(s)
+    assert lib.fd6_status_string(-99) == b"unknown status"
+
+
+def desc(nx=32, ny=32, nz=32, prec=1, var=0, flags=0):
+    import paper_1707_08900_amd as p
+    return p.Fd6Desc(nx, ny, nz, prec, var, flags)
+
+
+def test_workspace_bytes_validation(pkg):
+    lib = pkg.library()
+    out = ctypes.c_size_t()
+    assert lib.fd6_workspace_bytes(ctypes.byref(desc()), ctypes.byref(out)) == 0
+    fp32 = out.value
+    assert lib.fd6_workspace_bytes(ctypes.byref(desc(prec=0)), ctypes.byref(out)) == 0
+    assert out.value > fp32  # FP64 needs more
+    for bad in (desc(nx=5), desc(ny=0), desc(nz=4097), desc(prec=3), desc(var=2),
+                desc(flags=1)):
+        assert lib.fd6_workspace_bytes(ctypes.byref(bad), ctypes.byref(out)) == -1
+    assert lib.fd6_workspace_bytes(None, ctypes.byref(out)) == -1
+    assert lib.fd6_workspace_bytes(ctypes.byref(desc()), None) == -1
+
+
+def test_workspace_grows_with_19p_div_field(pkg):
+    lib = pkg.library()
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    lib.fd6_workspace_bytes(ctypes.byref(desc(var=0)), ctypes.byref(a))
+    lib.fd6_workspace_bytes(ctypes.byref(desc(var=1)), ctypes.byref(b))
+    assert b.value > a.value
+
+
+def test_create_validation_and_state_machine(pkg):
+    """Everything here stays in host code: fd6_create only carves the
+    workspace pointer, and validation precedes every device call."""
+    lib = pkg.library()
+    d = desc(nx=8, ny=8, nz=8, prec=0)
+    need = ctypes.c_size_t()
+    lib.fd6_workspace_bytes(ctypes.byref(d), ctypes.byref(need))
+    fake = ctypes.c_void_p(1 << 40)  # aligned, never dereferenced by create
+    h = ctypes.c_void_p()
+    assert lib.fd6_create(ctypes.byref(d), fake, need.value - 1, None, ctypes.byref(h)) == -3
+    assert lib.fd6_create(ctypes.byref(d), ctypes.c_void_p((1 << 40) + 8), need.value, None,
+                          ctypes.byref(h)) == -1
+    assert lib.fd6_create(ctypes.byref(d), None, need.value, None, ctypes.byref(h)) == -1
+    assert lib.fd6_create(ctypes.byref(d), fake, need.value, None, None) == -1
+    assert lib.fd6_create(ctypes.byref(d), fake, need.value, None, ctypes.byref(h)) == 0
+    try:
+        # step / get / reduce / rhs before params and fields
+        assert lib.fd6_rk3_step(h, 1) == -2
+        r = pkg.Fd6Reductions()
+        assert lib.fd6_reduce(h, ctypes.byref(r)) == -2
+        buf = (ctypes.c_double * 512)()
+        assert lib.fd6_get_fields(h, buf, buf, buf, buf) == -2
+        assert lib.fd6_rhs(h, buf, buf, buf, buf) == -2
+        assert lib.fd6_rk3_step(h, -1) == -1
+        # parameter validation
+        good = pkg.Fd6Params(1e-3, 1.0, 0.1, 0.1, 0.1, 0.01)
+        for field, val in (("nu", -1.0), ("cs", float("nan")), ("dx", 0.0), ("dy", -0.1),
+                           ("dz", float("inf")), ("dt", 0.0)):
+            p = pkg.Fd6Params(*[getattr(good, n) for n in ("nu", "cs", "dx", "dy", "dz", "dt")])
+            setattr(p, field, val)
+            assert lib.fd6_set_params(h, ctypes.byref(p)) == -1, field
+        assert lib.fd6_set_params(h, ctypes.byref(good)) == 0
+        assert lib.fd6_rk3_step(h, 1) == -2  # fields still missing
+        assert lib.fd6_init_fields(h, None, buf, buf, buf) == -1
+        # tile selection
+        n = lib.fd6_tile_count()
+        assert n >= 2
+        assert lib.fd6_set_tile(h, n) == -1
+        assert lib.fd6_set_tile(h, -1) == -1
+        assert lib.fd6_set_tile(h, 0) == 0
+        assert lib.fd6_last_error(h) == b""
+    finally:
+        assert lib.fd6_destroy(h) == 0
+    assert lib.fd6_destroy(None) == 0
+    assert lib.fd6_last_error(None) == b""

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances (per field, ||gpu - oracle||_inf / ||oracle||_inf):
+  FP64            1e-12 after one full step (3 substeps)
+  FP32            1e-5 after one step
+  FP32 + FP64 w   no worse than FP32
+FP32 inputs are the FP64 generator values rounded to float32 on the host by
+numpy; the oracle receives the same rounded values.
+"""
+import numpy as np
+import pytest
+
+import synthetic_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_acc64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def fd6():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible ROCm GPU")
+    import paper_1707_08900_amd as p
+    return p
+
+
+def rel_err(a, b):
+    return max(float(np.max(np.abs(x - y)) / max(np.max(np.abs(y)), 1e-300)) for x, y in zip(a, b))
+
+
+def oracle_inputs(fields, precision):
+    return si.as_float32_exact(fields) if precision != "fp64" else [np.array(f) for f in fields]
+
+
+def run_gpu(fd6, w, precision, variant="55p", nsteps=1, tile=None):
+    box = fd6.Box(w.shape, precision, variant)
+    if tile is not None:
+        box.set_tile(tile)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(w.fields)
+    box.step(nsteps)
+    out = box.get_fields()
+    box.close()
+    return out
+
+
+def run_oracle(orc, w, precision, variant="55p", nsteps=1):
+    return orc.rk3(oracle_inputs(w.fields, precision), w.nu, w.cs, w.dx, w.dy, w.dz, w.dt,
+                   variant, nsteps)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_acc64"])
+def test_small_box_one_step_all_kernels(fd6, orc, precision):
+    w = si.small_parity_box()
+    ref = run_oracle(orc, w, precision)
+    errs = {}
+    for tile in range(fd6.tile_count()):
+        out = run_gpu(fd6, w, precision, tile=tile)
+        errs[tile] = rel_err(out, ref)
+        print(f"32^3 {precision} tile {tile}: rel err {errs[tile]:.3e}", flush=True)
+    assert max(errs.values()) <= TOL[precision], errs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_increments_match(fd6, orc, precision):
+    """The change over one step (out - in), not only the state, matches."""
+    w = si.small_parity_box(seed=3)
+    ref = run_oracle(orc, w, precision)
+    out = run_gpu(fd6, w, precision)
+    base = oracle_inputs(w.fields, precision)
+    inc_ref = [r - b for r, b in zip(ref, base)]
+    inc_gpu = [o - b for o, b in zip(out, base)]
+    tol = 1e-10 if precision == "fp64" else 1e-2
+    assert rel_err(inc_gpu, inc_ref) <= tol
+
+
+@pytest.mark.parametrize("shape", [(23, 29, 37), (6, 6, 6), (7, 70, 9), (40, 6, 130)])
+def test_ragged_shapes_fp64(fd6, orc, shape):
+    """Tails that do not fill a tile, the minimum size, and tall/wide boxes."""
+    w = si.noise_box(shape, seed=5)
+    ref = run_oracle(orc, w, "fp64", nsteps=2)
+    for tile in range(fd6.tile_count()):
+        out = run_gpu(fd6, w, "fp64", nsteps=2, tile=tile)
+        e = rel_err(out, ref)
+        print(f"{shape} tile {tile}: {e:.3e}", flush=True)
+        assert e <= 1e-12, (shape, tile, e)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_19p_variant(fd6, orc, precision):
+    w = si.small_parity_box(seed=1)
+    ref = run_oracle(orc, w, precision, variant="19p")
+    out = run_gpu(fd6, w, precision, variant="19p")
+    e = rel_err(out, ref)
+    print(f"19p {precision}: {e:.3e}", flush=True)
+    assert e <= TOL[precision]
+
+
+def test_mid_box_several_steps_fp64(fd6, orc):
+    """128^3-style random-phase fields on a smaller grid, 5 steps."""
+    w = si.fourier_box(48, seed=0, amplitude=1e-2, kmax=8.0, nu=2e-3)
+    ref = run_oracle(orc, w, "fp64", nsteps=5)
+    for tile in range(1, fd6.tile_count()):
+        out = run_gpu(fd6, w, "fp64", nsteps=5, tile=tile)
+        assert rel_err(out, ref) <= 1e-11
+
+
+def test_sweep_tiles_are_bitwise_identical(fd6):
+    """Every z-sweep tile shape performs the same arithmetic per point."""
+    w = si.noise_box((20, 21, 70), seed=8)
+    outs = [run_gpu(fd6, w, "fp32", nsteps=2, tile=t) for t in range(1, fd6.tile_count())]
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_runs_are_deterministic(fd6):
+    w = si.noise_box((16, 24, 40), seed=9)
+    a = run_gpu(fd6, w, "fp32", nsteps=3)
+    b = run_gpu(fd6, w, "fp32", nsteps=3)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_rest_state_bitwise(fd6):
+    shape = (12, 10, 14)
+    f = [np.full(shape, 0.25), np.zeros(shape), np.zeros(shape), np.zeros(shape)]
+    for prec in ("fp64", "fp32"):
+        box = fd6.Box(shape, prec)
+        box.set_params(0.01, 1.0, 0.1, 0.1, 0.1, 0.05)
+        box.init_fields(f)
+        box.step(3)
+        out = box.get_fields()
+        for a, b in zip(out, si.as_float32_exact(f) if prec == "fp32" else f):
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("variant", ["55p", "19p"])
+def test_rhs_hook_fp64(fd6, orc, variant):
+    w = si.noise_box((18, 20, 22), seed=4)
+    box = fd6.Box(w.shape, "fp64", variant)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(w.fields)
+    r = box.rhs()
+    ref = orc.rhs(w.fields, w.nu, w.cs, w.dx, w.dy, w.dz, variant)
+    assert rel_err(r, ref) <= 1e-12
+    # the state is untouched by the hook
+    for a, b in zip(box.get_fields(), w.fields):
+        assert np.array_equal(a, b)
+
+
+def test_reductions_match_oracle(fd6, orc):
+    w = si.fourier_box(40, seed=2, amplitude=0.1, kmax=6.0)
+    for prec in ("fp64", "fp32"):
+        box = fd6.Box(w.shape, prec)
+        box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+        box.init_fields(w.fields)
+        g = box.reduce()
+        o = orc.reduce(oracle_inputs(w.fields, prec), w.dx, w.dy, w.dz)
+        assert g["mass"] == pytest.approx(o["mass"], rel=1e-13)
+        assert g["kinetic_energy"] == pytest.approx(o["kinetic_energy"], rel=1e-13)
+        scale = np.sum(np.abs(oracle_inputs(w.fields, prec)[0]))
+        assert abs(g["sum_lnrho"] - o["sum_lnrho"]) <= 1e-13 * scale
+        assert g["umax"] == o["umax"]
+        assert g["nonfinite"] == 0
+        # repeated reductions are bitwise identical
+        assert box.reduce() == g
+
+
+def test_reduce_reports_nonfinite(fd6):
+    shape = (8, 8, 8)
+    f = [np.zeros(shape) for _ in range(4)]
+    f[1][1, 2, 3] = np.nan
+    f[3][4, 4, 4] = np.inf
+    box = fd6.Box(shape, "fp64")
+    box.set_params(0.01, 1.0, 0.1, 0.1, 0.1, 0.01)
+    box.init_fields(f)
+    with pytest.raises(fd6.Fd6Error) as e:
+        box.reduce()
+    assert e.value.status == -5
+    assert box.reduce(allow_nonfinite=True)["nonfinite"] == 2
+
+
+def test_checkpoint_restart_bitwise(fd6):
+    """10 steps == 5 steps, get_fields / init_fields, 5 steps (w carries no
+    state across steps because alpha(1) = 0)."""
+    w = si.noise_box((16, 16, 16), seed=6)
+    box = fd6.Box(w.shape, "fp64")
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(w.fields)
+    box.step(10)
+    full = box.get_fields()
+    box.init_fields(w.fields)
+    box.step(5)
+    mid = box.get_fields()
+    box.init_fields(mid)
+    box.step(5)
+    for a, b in zip(box.get_fields(), full):
+        assert np.array_equal(a, b)
+
+
+def test_device_init_and_export(fd6):
+    import torch
+    w = si.noise_box((10, 12, 14), seed=12)
+    box = fd6.Box(w.shape, "fp64")
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields([torch.from_numpy(f).cuda() for f in w.fields])
+    box.step(1)
+    dev = [t.cpu().numpy() for t in box.get_fields_device()]
+    host = box.get_fields()
+    for a, b in zip(dev, host):
+        assert np.array_equal(a, b)
