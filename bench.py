@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the full RK3 step on one MI355X.
+
+Workload (the single-box FP32 throughput configuration): a 512^3 periodic
+box, FP32 storage and arithmetic, 55-point discretisation, fields lnrho and u
+as sums of 16 random-phase Fourier modes with |k| <= 16 and amplitude 0.1,
+nu = 1e-3, cs = 1, dt = 0.4 CFL, and FP64 global reductions (mass, kinetic
+energy, sum lnrho, max |u|, non-finite count) computed on the device after
+every step.  One step = 3 substeps, each a periodic ghost fill plus the
+fused right-hand-side + 2N-RK3 kernel, then the reductions.
+
+Prints ONE JSON line (metric, value in grid-point updates/s, roofline of the
+dominant kernel measured with HIP events on its stream, the FP64 oracle's
+rate on the host CPU, and the other precision forms on the same GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per grid-point update (one full RK3 step), the
+# method's own minimum: state read once per substep, w read when alpha != 0
+# and written when it is needed again, output written once; ghosts and halo
+# re-reads excluded.  55-point: 40 field accesses per step; 19-point: 76.
+ALG_BYTES = {("55p", "fp32"): 160, ("55p", "fp64"): 320, ("55p", "fp32_acc64"): 224,
+             ("19p", "fp32"): 304, ("19p", "fp64"): 608}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_substep55_fp32_512.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1707_08900_amd", "csrc", "substep55.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != source_sha(KERNEL_SRC):
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def make_box(fd6, w, dev_fields, precision, variant, tune=True):
+    box = fd6.Box(w.shape, precision, variant)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    tuned = None
+    if tune and variant == "55p":
+        from paper_1707_08900_amd import tune as tuner
+        box.init_fields(dev_fields)
+        tuned = tuner.tune(box, steps=2, use_cache=False)
+    box.init_fields(dev_fields)
+    return box, tuned
+
+
+def timed_steps(torch, box, red, steps, warmup, timing=True):
+    for _ in range(warmup):
+        box.step_reduce(1, red)
+    torch.cuda.synchronize()
+    if timing:
+        box.set_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(box.stream)
+    for _ in range(steps):
+        box.step_reduce(1, red)
+    e1.record(box.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    tm = box.get_timing() if timing else None
+    if timing:
+        box.set_timing(False)
+    return wall, ev_ms, tm
+
+
+def sample_error(orc, fd6, si, w, dev_fields, precision, variant, nsamples=6):
+    """Max over sampled points of |gpu - oracle| / max|field| after one step
+    from the workload's initial state (oracle on local patches)."""
+    import numpy as np
+    box, _ = make_box(fd6, w, dev_fields, precision, variant, tune=False)
+    box.step(1)
+    out = box.get_fields_device()
+    box.close()
+    inp = si.as_float32_exact(w.fields) if precision != "fp64" else w.fields
+    rng = np.random.default_rng(123)
+    nz, ny, nx = w.shape
+    worst = 0.0
+    scale = [max(float(np.max(np.abs(f))), 1e-300) for f in inp]
+    for _ in range(nsamples):
+        c = (int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx)))
+        ref = orc.rk3_point(inp, c, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, variant, 1)
+        for q in range(4):
+            worst = max(worst, abs(float(out[q][c].item()) - ref[q]) / scale[q])
+    return worst
+
+
+def cpu_baseline(orc, si, w, threads):
+    """FP64 oracle rate on a bounded sample of the workload: its first 128
+    z-planes as a periodic 512 x 512 x 128 box, one full RK3 step."""
+    nzs = min(128, w.shape[0])
+    sample = [f[:nzs].copy() for f in w.fields]
+    orc.rk3(sample[:], w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, threads)  # page-in
+    t0 = time.perf_counter()
+    orc.rk3(sample, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, threads)
+    dt = time.perf_counter() - t0
+    pts = nzs * w.shape[1] * w.shape[2]
+    return {"value": pts / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {nzs} z-planes of the workload as a periodic "
+                      f"{w.shape[2]}x{w.shape[1]}x{nzs} box, one RK3 step, FP64 C oracle "
+                      f"with {threads} OpenMP threads ({dt:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP64/ACC64/19p forms")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    a = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the single-box kernel runs on one MI355X; see DESIGN.md for how it would "
+              "shard). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1707_08900_amd as fd6
+    import synthetic_inputs as si
+
+    n = a.size
+    t0 = time.perf_counter()
+    w = si.large_box(n)
+    log(f"inputs {n}^3 generated in {time.perf_counter() - t0:.1f} s; dt = {w.dt:.4e}")
+
+    if a.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    dev_fields = [torch.from_numpy(f).cuda() for f in w.fields]
+    red = torch.zeros(8, dtype=torch.float64, device="cuda")
+    box, tuned = make_box(fd6, w, dev_fields, "fp32", "55p")
+    log(f"tuned kernel shape: {tuned}")
+    wall, ev_ms, (kms, klaunch, gms, glaunch) = timed_steps(torch, box, red, a.steps, a.warmup)
+    r = red.cpu().numpy()
+    box.close()
+    ms_per_step = ev_ms / a.steps
+    value = n ** 3 * a.steps / (ev_ms * 1e-3)
+    log(f"fp32 55p {n}^3: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} G updates/s "
+        f"(host wall {wall * 1e3 / a.steps:.3f} ms/step); mass {r[0]:.10e} ke {r[1]:.6e}")
+
+    # dominant kernel: the fused 55-point substep kernel
+    alg_per_launch = n ** 3 * ALG_BYTES[("55p", "fp32")] / 3.0
+    avg_launch_s = kms * 1e-3 / klaunch
+    achieved = alg_per_launch / avg_launch_s / 1e9
+    traffic = load_traffic()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernel": "substep55_sweep (fused RHS + RK3)",
+                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": klaunch,
+                "alg_bytes_per_launch": alg_per_launch,
+                "ghost_fill_us_per_launch": round(gms * 1e3 / max(glaunch, 1), 2)}
+
+    import oracle
+    forms = {}
+    step_alg = ALG_BYTES[("55p", "fp32")]
+    forms["fp32"] = {"updates_per_s": value, "ms_per_step": ms_per_step,
+                     "hbm_frac_step": value * step_alg / (HBM_PEAK_GBS * 1e9)}
+    if not a.no_check:
+        forms["fp32"]["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields, "fp32", "55p")
+    if not a.no_forms:
+        k2 = max(5, a.steps // 5)
+        for prec, var in (("fp64", "55p"), ("fp32_acc64", "55p"), ("fp32", "19p"),
+                          ("fp64", "19p")):
+            b2, tn = make_box(fd6, w, dev_fields, prec, var)
+            wl, em, tm = timed_steps(torch, b2, red, k2, 2)
+            b2.close()
+            v = n ** 3 * k2 / (em * 1e-3)
+            entry = {"updates_per_s": v, "ms_per_step": em / k2,
+                     "hbm_frac_step": v * ALG_BYTES[(var, prec)] / (HBM_PEAK_GBS * 1e9),
+                     "speed_vs_fp64_55p": None}
+            if not a.no_check:
+                entry["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields, prec, var)
+            forms[f"{prec}_{var}"] = entry
+            log(f"{prec} {var}: {em / k2:.3f} ms/step, {v / 1e9:.2f} G updates/s")
+        base64 = forms["fp64_55p"]["updates_per_s"]
+        forms["fp32"]["speed_vs_fp64_55p"] = value / base64
+        for k, e in forms.items():
+            if k != "fp32":
+                e["speed_vs_fp64_55p"] = e["updates_per_s"] / base64
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        oracle.build(force=False)
+        cpu = cpu_baseline(oracle, si, w, threads)
+        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M updates/s on {threads} threads")
+
+    out = {
+        "metric": "grid-point updates/s per full RK3 step + % HBM roofline (FP64 vs FP32 vs batched)",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}^3 periodic box, FP32, 55-point fused substep, 16 random-phase "
+                               f"modes |k|<=16 A=0.1, nu=1e-3, cs=1, dt=0.4 CFL, FP64 reductions "
+                               f"every step",
+                   "grid": [n, n, n], "precision": "fp32", "variant": "55p",
+                   "kernel_shape": tuned},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "hbm_frac_step": value * step_alg / (HBM_PEAK_GBS * 1e9),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -124,10 +124,18 @@ int fd6_init_fields(fd6_box *box, const double *lnrho, const double *ux, const d
 int fd6_init_fields_device(fd6_box *box, const double *lnrho, const double *ux,
                            const double *uy, const double *uz);
 
-/* Advance nsteps >= 0 full RK3 steps (3 substeps each: periodic ghost fill,
- * then the fused right-hand side + 2N-RK3 update, Algorithm 2; or the two
- * passes of Algorithm 3).  Asynchronous on the box's stream. */
+/* Advance nsteps >= 0 full RK3 steps (3 substeps each: periodic boundary
+ * condition, then the fused right-hand side + 2N-RK3 update, Algorithm 2; or
+ * the two passes of Algorithm 3).  The z-sweep kernels resolve the periodic
+ * images while loading their tiles; kernels that read the 3-cell ghost zone
+ * are preceded by the periodic ghost pass.  Asynchronous on the box's
+ * stream. */
 int fd6_rk3_step(fd6_box *box, int32_t nsteps);
+
+/* Advance nsteps >= 1 steps like fd6_rk3_step and enqueue the FP64
+ * diagnostics of the final state (layout of fd6_reduce_device) into the
+ * device buffer d_out5.  Asynchronous. */
+int fd6_rk3_step_reduce(fd6_box *box, int32_t nsteps, double *d_out5);
 
 /* Copy the state to host FP64 arrays.  Synchronises. */
 int fd6_get_fields(fd6_box *box, double *lnrho, double *ux, double *uy, double *uz);
@@ -139,6 +147,11 @@ int fd6_get_fields_device(fd6_box *box, double *lnrho, double *ux, double *uy, d
  * order).  Synchronises.  Returns FD6_ENONFINITE (with *out filled) when
  * out->nonfinite > 0. */
 int fd6_reduce(fd6_box *box, fd6_reductions *out);
+
+/* Same diagnostics written asynchronously, on the box's stream, to a device
+ * buffer of 5 doubles: mass, kinetic energy, sum lnrho, max |u|, non-finite
+ * count (as a double).  For use inside a timed or captured sequence. */
+int fd6_reduce_device(fd6_box *box, double *d_out5);
 
 /* Right-hand side d/dt (lnrho, ux, uy, uz) of the current state, evaluated by
  * the same kernels as a substep (precision of the box), to host FP64 arrays.
@@ -152,6 +165,15 @@ int fd6_rhs(fd6_box *box, double *r_lnrho, double *r_ux, double *r_uy, double *r
  * order; the choice only changes speed (see the autotuner). */
 int fd6_tile_count(void);
 int fd6_set_tile(fd6_box *box, int32_t tile);
+
+/* Kernel timing with HIP events recorded on the box's stream around every
+ * launch of the main substep kernel(s) (55-point fused kernel; both passes of
+ * the 19-point method) and of the ghost fill.  enable != 0 starts (and
+ * resets) collection, 0 stops it.  fd6_get_timing synchronises and returns
+ * the summed milliseconds and launch counts since collection started. */
+int fd6_set_timing(fd6_box *box, int enable);
+int fd6_get_timing(fd6_box *box, double *kernel_ms, int64_t *kernel_launches, double *ghost_ms,
+                   int64_t *ghost_launches);
 
 /* Text of the last error on this handle ("" if none). */
 const char *fd6_last_error(const fd6_box *box);

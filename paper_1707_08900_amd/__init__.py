@@ -28,8 +28,9 @@ STATUS = {0: "FD6_OK", -1: "FD6_EINVAL", -2: "FD6_ESTATE", -3: "FD6_ENOMEM", -4:
 ABI_SYMBOLS = (
     "fd6_abi_version", "fd6_status_string", "fd6_workspace_bytes", "fd6_create", "fd6_destroy",
     "fd6_set_stream", "fd6_set_params", "fd6_init_fields", "fd6_init_fields_device",
-    "fd6_rk3_step", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
-    "fd6_tile_count", "fd6_set_tile", "fd6_last_error",
+    "fd6_rk3_step", "fd6_rk3_step_reduce", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
+    "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_timing", "fd6_get_timing",
+    "fd6_last_error",
 )
 
 
@@ -71,10 +72,15 @@ def _declare(lib):
         "fd6_init_fields": (I, [P, D, D, D, D]),
         "fd6_init_fields_device": (I, [P, P, P, P, P]),
         "fd6_rk3_step": (I, [P, ctypes.c_int32]),
+        "fd6_rk3_step_reduce": (I, [P, ctypes.c_int32, P]),
         "fd6_get_fields": (I, [P, D, D, D, D]),
         "fd6_get_fields_device": (I, [P, P, P, P, P]),
         "fd6_reduce": (I, [P, ctypes.POINTER(Fd6Reductions)]),
         "fd6_rhs": (I, [P, D, D, D, D]),
+        "fd6_reduce_device": (I, [P, P]),
+        "fd6_set_timing": (I, [P, I]),
+        "fd6_get_timing": (I, [P, D, ctypes.POINTER(ctypes.c_int64), D,
+                                ctypes.POINTER(ctypes.c_int64)]),
         "fd6_tile_count": (I, []),
         "fd6_set_tile": (I, [P, ctypes.c_int32]),
         "fd6_last_error": (ctypes.c_char_p, [P]),
@@ -188,6 +194,14 @@ class Box:
     def step(self, nsteps: int = 1):
         self._check(self.lib.fd6_rk3_step(self.h, int(nsteps)), "fd6_rk3_step")
 
+    def step_reduce(self, nsteps: int, out: torch.Tensor):
+        """Advance and leave the FP64 diagnostics of the final state in `out`
+        (float64 device tensor, >= 5 elements), asynchronously."""
+        assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= 5
+        self._check(self.lib.fd6_rk3_step_reduce(self.h, int(nsteps),
+                                                 ctypes.c_void_p(out.data_ptr())),
+                    "fd6_rk3_step_reduce")
+
     def get_fields(self):
         out = [np.empty(self.shape) for _ in range(4)]
         self._check(self.lib.fd6_get_fields(self.h, *[_dptr(a) for a in out]), "fd6_get_fields")
@@ -211,6 +225,22 @@ class Box:
             self._check(rc, "fd6_reduce")
         return {"mass": r.mass, "kinetic_energy": r.kinetic_energy, "sum_lnrho": r.sum_lnrho,
                 "umax": r.umax, "nonfinite": int(r.nonfinite)}
+
+    def reduce_device(self, out: torch.Tensor):
+        """Enqueue the FP64 diagnostics into a 5-element float64 device tensor."""
+        assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= 5
+        self._check(self.lib.fd6_reduce_device(self.h, ctypes.c_void_p(out.data_ptr())),
+                    "fd6_reduce_device")
+
+    def set_timing(self, enable: bool):
+        self._check(self.lib.fd6_set_timing(self.h, 1 if enable else 0), "fd6_set_timing")
+
+    def get_timing(self):
+        """(kernel_ms, kernel_launches, ghost_ms, ghost_launches) since set_timing(True)."""
+        km, kn, gm, gn = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.fd6_get_timing(self.h, ctypes.byref(km), ctypes.byref(kn),
+                                            ctypes.byref(gm), ctypes.byref(gn)), "fd6_get_timing")
+        return km.value, kn.value, gm.value, gn.value
 
     def set_tile(self, tile: int):
         self._check(self.lib.fd6_set_tile(self.h, int(tile)), "fd6_set_tile")

@@ -144,29 +144,32 @@ __device__ inline void block_reduce_store(RedAcc acc, double* out) {
     }
 }
 
+// Each block takes whole x rows (row r = blockIdx.x, blockIdx.x + gridDim.x,
+// ...), threads stride along the row: coalesced loads, one division per row.
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(Geom g, Fields4<T> f,
                                                                       double* partials,
                                                                       long long count) {
+    (void)count;
     RedAcc acc{0.0, 0.0, 0.0, 0.0, 0.0};
-    const long long e0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (long long e = e0; e < count; e += (long long)gridDim.x * blockDim.x) {
-        long long r = e / g.nx;
-        int i = (int)(e - r * g.nx);
-        int j = (int)(r % g.ny);
-        long long k = r / g.ny;
-        long long c = g.origin + k * g.plane + (long long)j * g.px + i;
-        double lr = (double)f.f[0][c], ux = (double)f.f[1][c], uy = (double)f.f[2][c],
-               uz = (double)f.f[3][c];
-        double rho = exp(lr);
-        double u2 = ux * ux + uy * uy + uz * uz;
-        acc.mass += rho;
-        acc.ke += 0.5 * rho * u2;
-        acc.slr += lr;
-        double um = sqrt(u2);
-        acc.umax = um > acc.umax ? um : acc.umax;
-        bool finite = isfinite(lr) && isfinite(ux) && isfinite(uy) && isfinite(uz);
-        acc.bad += finite ? 0.0 : 1.0;
+    const int rows = g.ny * g.nz;
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int k = r / g.ny, j = r - k * g.ny;
+        const long long base = g.origin + (long long)k * g.plane + (long long)j * g.px;
+        for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
+            const long long c = base + i;
+            const double lr = (double)f.f[0][c], ux = (double)f.f[1][c], uy = (double)f.f[2][c],
+                         uz = (double)f.f[3][c];
+            const double rho = exp(lr);
+            const double u2 = ux * ux + uy * uy + uz * uz;
+            acc.mass += rho;
+            acc.ke += 0.5 * rho * u2;
+            acc.slr += lr;
+            const double um = sqrt(u2);
+            acc.umax = um > acc.umax ? um : acc.umax;
+            const bool finite = isfinite(lr) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+            acc.bad += finite ? 0.0 : 1.0;
+        }
     }
     block_reduce_store(acc, partials + (size_t)blockIdx.x * kReduceSlots);
 }

@@ -13,6 +13,8 @@
 #include <exception>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/fd6.h"
 #include "fd6_internal.hpp"
@@ -38,8 +40,18 @@ struct fd6_box {
     double* staging = nullptr;
     long long staging_elems = 0;
     int cur = 0;
-    int tile = 1;
+    int tile = 4;
+    bool ghosts_ok[2] = {false, false};  // ghost zone of each state set is current
     std::string err;
+    // optional per-launch event timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_kernel, ev_ghost;
+    std::vector<hipEvent_t> ev_pool;
+    ~fd6_box() {
+        for (auto& p : ev_kernel) ev_pool.push_back(p.first), ev_pool.push_back(p.second);
+        for (auto& p : ev_ghost) ev_pool.push_back(p.first), ev_pool.push_back(p.second);
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -139,6 +151,29 @@ int hip_fail(fd6_box* b, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail((b), e_, #expr); \
     } while (0)
 
+hipError_t take_event(fd6_box* b, hipEvent_t* e) {
+    if (!b->ev_pool.empty()) {
+        *e = b->ev_pool.back();
+        b->ev_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Records an event pair around the launches made by f when timing is on.
+template <typename F>
+int timed(fd6_box* b, std::vector<std::pair<hipEvent_t, hipEvent_t>>& log, F&& f) {
+    if (!b->timing) return f();
+    hipEvent_t e0, e1;
+    HIPCHK(b, take_event(b, &e0));
+    HIPCHK(b, take_event(b, &e1));
+    HIPCHK(b, hipEventRecord(e0, b->stream));
+    int rc = f();
+    HIPCHK(b, hipEventRecord(e1, b->stream));
+    log.emplace_back(e0, e1);
+    return rc;
+}
+
 // RK3 coefficients of the 2N-storage scheme (Williamson 1980), alpha(1) = 0.
 constexpr double kAlpha[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 constexpr double kBeta[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
@@ -195,34 +230,69 @@ Fields4<T> fields_of(void* const f[4]) {
     return r;
 }
 
+// One substep: boundary condition (the ghost pass runs only for kernels that
+// read the ghost zone and only when it is stale), the substep kernel(s), and
+// the in/out swap.  With red_out != nullptr (substep 3) the FP64 diagnostics
+// of the new state are written to red_out (device, 5 doubles).
 template <typename T, typename TW>
-int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk) {
+int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullptr) {
     const Geom& g = b->geom;
     Fields4<T> in = fields_of<T>(b->state[b->cur]);
     Fields4<T> out = fields_of<T>(b->state[b->cur ^ 1]);
     Fields4<TW> w = fields_of<TW>(b->w);
     const Coef<T> c = make_coef<T>(b->params);
-    HIPCHK(b, launch_ghost_fill<T>(g, in, 4, b->stream));
+    const bool needs_ghosts = b->desc.variant == FD6_19P || substep55_reads_ghosts(b->tile);
+    int rc = FD6_OK;
+    if (needs_ghosts && !b->ghosts_ok[b->cur]) {
+        rc = timed(b, b->ev_ghost, [&]() -> int {
+            HIPCHK(b, launch_ghost_fill<T>(g, in, 4, b->stream));
+            return FD6_OK;
+        });
+        if (rc) return rc;
+        b->ghosts_ok[b->cur] = true;
+    }
     if (b->desc.variant == FD6_55P) {
-        HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->stream)));
+        rc = timed(b, b->ev_kernel, [&]() -> int {
+            HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->stream)));
+            return FD6_OK;
+        });
+        if (rc) return rc;
     } else {
         T* dv = static_cast<T*>(b->div);
-        HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->stream)));
+        rc = timed(b, b->ev_kernel, [&]() -> int {
+            HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->stream)));
+            return FD6_OK;
+        });
+        if (rc) return rc;
         Fields4<T> d1{{dv, dv, dv, dv}};
-        HIPCHK(b, launch_ghost_fill<T>(g, d1, 1, b->stream));
-        HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, b->stream)));
+        rc = timed(b, b->ev_ghost, [&]() -> int {
+            HIPCHK(b, launch_ghost_fill<T>(g, d1, 1, b->stream));
+            return FD6_OK;
+        });
+        if (rc) return rc;
+        rc = timed(b, b->ev_kernel, [&]() -> int {
+            HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, b->stream)));
+            return FD6_OK;
+        });
+        if (rc) return rc;
     }
+    b->ghosts_ok[b->cur ^ 1] = false;  // no kernel writes the output ghost zone
     b->cur ^= 1;
+    if (red_out && s == 3) {
+        const double dV = b->params.dx * b->params.dy * b->params.dz;
+        HIPCHK(b, launch_reduce<T>(g, fields_of<T>(b->state[b->cur]), b->partials, red_out, dV,
+                                   b->stream));
+    }
     return FD6_OK;
 }
 
 template <typename T, typename TW>
-int do_steps(fd6_box* b, int nsteps) {
+int do_steps(fd6_box* b, int nsteps, double* red_out = nullptr) {
     const double dt = b->params.dt;
     for (int n = 0; n < nsteps; ++n)
         for (int s = 0; s < 3; ++s) {
             RKCoef<TW> rk{TW(kAlpha[s]), TW(kBeta[s]), TW(dt)};
-            int rc = do_substep<T, TW>(b, s + 1, rk);
+            int rc = do_substep<T, TW>(b, s + 1, rk, n == nsteps - 1 ? red_out : nullptr);
             if (rc) return rc;
         }
     return FD6_OK;
@@ -235,6 +305,7 @@ int do_rhs(fd6_box* b, double* const out[4]) {
     RKCoef<TW> rk{TW(0), TW(0), TW(1)};
     int rc = do_substep<T, TW>(b, 1, rk);
     b->cur ^= 1;  // keep the original state current
+    b->ghosts_ok[b->cur ^ 1] = false;
     if (rc) return rc;
     const Geom& g = b->geom;
     const long long n = (long long)g.nx * g.ny * g.nz;
@@ -332,6 +403,15 @@ int do_reduce(fd6_box* b, fd6_reductions* out) {
     out->umax = r[3];
     out->nonfinite = (int64_t)r[4];
     return out->nonfinite > 0 ? FD6_ENONFINITE : FD6_OK;
+}
+
+template <typename T>
+int do_reduce_device(fd6_box* b, double* d_out) {
+    const Geom& g = b->geom;
+    const double dV = b->params.dx * b->params.dy * b->params.dz;
+    HIPCHK(b, launch_reduce<T>(g, fields_of<T>(b->state[b->cur]), b->partials, d_out, dV,
+                               b->stream));
+    return FD6_OK;
 }
 
 // Precision dispatch: FP64 -> (double, double); FP32 -> (float, float);
@@ -447,6 +527,7 @@ int fd6_init_fields(fd6_box* b, const double* lnrho, const double* ux, const dou
     return guarded(b, [&]() -> int {
         const double* src[4] = {lnrho, ux, uy, uz};
         b->cur = 0;
+        b->ghosts_ok[0] = b->ghosts_ok[1] = false;
         int rc = dispatch(b, [&](auto* t, auto*) -> int {
             using T = std::remove_pointer_t<decltype(t)>;
             return import_host<T>(b, src);
@@ -466,6 +547,7 @@ int fd6_init_fields_device(fd6_box* b, const double* lnrho, const double* ux, co
     return guarded(b, [&]() -> int {
         const double* src[4] = {lnrho, ux, uy, uz};
         b->cur = 0;
+        b->ghosts_ok[0] = b->ghosts_ok[1] = false;
         int rc = dispatch(b, [&](auto* t, auto*) -> int {
             using T = std::remove_pointer_t<decltype(t)>;
             return import_device<T>(b, src);
@@ -486,6 +568,18 @@ int fd6_rk3_step(fd6_box* b, int32_t nsteps) {
             using T = std::remove_pointer_t<decltype(t)>;
             using TW = std::remove_pointer_t<decltype(tw)>;
             return do_steps<T, TW>(b, nsteps);
+        });
+    });
+}
+
+int fd6_rk3_step_reduce(fd6_box* b, int32_t nsteps, double* d_out5) {
+    if (!b || nsteps < 1 || !d_out5) return FD6_EINVAL;
+    if (!ready(b)) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        return dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            return do_steps<T, TW>(b, nsteps, d_out5);
         });
     });
 }
@@ -522,6 +616,51 @@ int fd6_reduce(fd6_box* b, fd6_reductions* out) {
             using T = std::remove_pointer_t<decltype(t)>;
             return do_reduce<T>(b, out);
         });
+    });
+}
+
+int fd6_reduce_device(fd6_box* b, double* d_out5) {
+    if (!b || !d_out5) return FD6_EINVAL;
+    if (!ready(b)) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        return dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return do_reduce_device<T>(b, d_out5);
+        });
+    });
+}
+
+int fd6_set_timing(fd6_box* b, int enable) {
+    if (!b) return FD6_EINVAL;
+    for (auto& p : b->ev_kernel) b->ev_pool.push_back(p.first), b->ev_pool.push_back(p.second);
+    for (auto& p : b->ev_ghost) b->ev_pool.push_back(p.first), b->ev_pool.push_back(p.second);
+    b->ev_kernel.clear();
+    b->ev_ghost.clear();
+    b->timing = enable != 0;
+    return FD6_OK;
+}
+
+int fd6_get_timing(fd6_box* b, double* kernel_ms, int64_t* kernel_launches, double* ghost_ms,
+                   int64_t* ghost_launches) {
+    if (!b || !kernel_ms || !kernel_launches || !ghost_ms || !ghost_launches) return FD6_EINVAL;
+    return guarded(b, [&]() -> int {
+        HIPCHK(b, hipStreamSynchronize(b->stream));
+        double tk = 0.0, tg = 0.0;
+        for (auto& p : b->ev_kernel) {
+            float ms = 0.f;
+            HIPCHK(b, hipEventElapsedTime(&ms, p.first, p.second));
+            tk += ms;
+        }
+        for (auto& p : b->ev_ghost) {
+            float ms = 0.f;
+            HIPCHK(b, hipEventElapsedTime(&ms, p.first, p.second));
+            tg += ms;
+        }
+        *kernel_ms = tk;
+        *kernel_launches = (int64_t)b->ev_kernel.size();
+        *ghost_ms = tg;
+        *ghost_launches = (int64_t)b->ev_ghost.size();
+        return FD6_OK;
     });
 }
 

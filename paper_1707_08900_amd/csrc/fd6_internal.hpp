@@ -97,6 +97,9 @@ template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                             const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
                             hipStream_t st);
+// Whether a kernel shape reads the ghost zone of its input (the z-sweep
+// shapes resolve the periodic images in their loader instead).
+bool substep55_reads_ghosts(int tile);
 
 // 19-point method: pass 1 (divergence, partial update) and pass 2.
 template <typename T, typename TW>
@@ -112,6 +115,7 @@ constexpr int kReduceSlots = 8;  // mass, ke, sum lnrho, umax, nonfinite, pad
 template <typename T>
 hipError_t launch_reduce(const Geom& g, Fields4<T> f, double* partials, double* result,
                          double dV, hipStream_t s);
+
 
 int substep55_tile_count();
 

@@ -25,6 +25,8 @@
 //  * The z loop is unrolled by 8 so every ring index is a compile-time
 //    register; the workgroup-to-tile map keeps neighbouring tiles on one XCD
 //    so y-halo rows are served from that XCD's L2.
+#include <cstdlib>
+
 #include "fd6_internal.hpp"
 
 namespace fd6 {
@@ -205,6 +207,13 @@ struct SweepCtx {
     unsigned plane_bytes, wplane_bytes;
 };
 
+
+// Element index of the ghost corner (-3, -3) of interior plane p mod nz.
+__device__ __forceinline__ long long plane_corner(const Geom& g, int p) {
+    const int pz = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
+    return g.origin + (long long)pz * g.plane - kR * g.px - kR;
+}
+
 template <typename T, int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_prefetch(SweepRegs<T, NH>& R, const SweepCtx<T, TX, TY>& X,
                                                const Fields4<T>& in, long long corner) {
@@ -253,7 +262,7 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     }
     // next plane -> registers
     if (t + 1 < nplanes)
-        sweep_prefetch<T, TX, TY, NH>(R, X, in, g.origin + (long long)(p + 1) * g.plane - kR * g.px - kR);
+        sweep_prefetch<T, TX, TY, NH>(R, X, in, plane_corner(g, p + 1));
     __syncthreads();
 
     // ---- plane quantities of plane p for this thread's column ----
@@ -403,10 +412,12 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     const T u[3] = {R.q[1][sl8(PH - 3)], R.q[2][sl8(PH - 3)], R.q[3][sl8(PH - 3)]};
     T r[4];
     assemble_rhs(u, gr, J, Lf, cf.nu, cf.cs2, r);
+    // ghost corner (-3, -3) of output plane o
+    const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
         const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv[f], rk);
-        bstore(v, plane_rsrc(out.f[f] + g.origin + (long long)o * g.plane, X.plane_bytes), X.lane_o);
+        bstore(v, plane_rsrc(out.f[f] + ocorner, X.plane_bytes), X.lane_o);
         if constexpr (S != 3)
             bstore(wv[f], plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes), X.lane_w);
     }
@@ -416,7 +427,7 @@ template <typename T, typename TW, int TX, int TY, int S>
 __global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out,
                                                           Fields4<TW> w, Coef<T> cf,
                                                           RKCoef<TW> rk, int ntx, int nty,
-                                                          int zlen) {
+                                                          int zlen, int remap) {
     using Sh = SweepShape<T, TX, TY>;
     constexpr int NH = Sh::NH;
     __shared__ T lds[2 * 4 * Sh::FS];
@@ -425,7 +436,7 @@ __global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in,
     // go to the same XCD, which receives every 8th workgroup
     int b = blockIdx.x;
     const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    if (remap && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
     const int tix = b % ntx;
     const int tiy = (b / ntx) % nty;
     const int ch = b / (ntx * nty);
@@ -436,13 +447,20 @@ __global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in,
 
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     SweepCtx<T, TX, TY> X;
-    const int wxg = g.nx + 2 * kR;  // ghosted row extent
     X.plane_bytes = (unsigned)(g.plane * (long long)sizeof(T));
     X.wplane_bytes = (unsigned)(g.wplane * (long long)sizeof(TW));
-    {
-        const int ix = x0 + tx + kR, iy = y0 + ty + kR;  // from the ghost corner
-        X.goff_int = ix < wxg ? (unsigned)((iy * g.px + ix) * (int)sizeof(T)) : kDropOffset;
-    }
+    // Periodic boundary condition (Sec. 4) resolved in the loader: a halo cell
+    // outside the interior reads its periodic image, so this kernel neither
+    // reads nor needs the ghost zone.  Offsets are taken from the ghost corner
+    // (-3, -3) of a plane; cells beyond x < nx + 3, y < ny + 3 are never used
+    // by a stored point and are dropped.
+    auto wrapped_off = [&](int gx, int gy) -> unsigned {  // gx, gy in [-3, ...)
+        if (gx >= g.nx + kR || gy >= g.ny + kR) return kDropOffset;
+        const int ix = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+        const int iy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+        return (unsigned)(((iy + kR) * g.px + (ix + kR)) * (int)sizeof(T));
+    };
+    X.goff_int = wrapped_off(x0 + tx, y0 + ty);
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
         const int e = threadIdx.x + h * Sh::NT;
@@ -458,15 +476,17 @@ __global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in,
             c = cc < kR ? cc : cc + TX;
         }
         const bool in_range = e < Sh::HALO;
-        const int ix = x0 + c, iy = y0 + r;  // from the ghost corner
-        X.goff_h[h] = (in_range && ix < wxg) ? (unsigned)((iy * g.px + ix) * (int)sizeof(T))
-                                             : kDropOffset;
+        X.goff_h[h] = in_range ? wrapped_off(x0 - kR + c, y0 - kR + r) : kDropOffset;
         X.loff_h[h] = in_range ? r * Sh::W + c : Sh::PLANE;
     }
     {
         const int xo = x0 + tx, yo = y0 + ty;
         const bool store = xo < g.nx && yo < g.ny;
-        X.lane_o = store ? (unsigned)((yo * g.px + xo) * (int)sizeof(T)) : kDropOffset;
+        // state offsets are taken from the ghost corner (-3, -3) of the plane
+        auto soff = [&](int x, int y) {
+            return (unsigned)(((y + kR) * g.px + (x + kR)) * (int)sizeof(T));
+        };
+        X.lane_o = store ? soff(xo, yo) : kDropOffset;
         X.lane_w = store ? (unsigned)((yo * g.wpx + xo) * (int)sizeof(TW)) : kDropOffset;
     }
 
@@ -484,8 +504,7 @@ __global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in,
         for (int s = 0; s < 8; ++s) R.L[i][s] = T(0);
 
     const int nplanes = (ze - zb) + 2 * kR;
-    sweep_prefetch<T, TX, TY, NH>(R, X, in,
-                                  g.origin + (long long)(zb - kR) * g.plane - kR * g.px - kR);
+    sweep_prefetch<T, TX, TY, NH>(R, X, in, plane_corner(g, zb - kR));
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
         sweep_step<0, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
         sweep_step<1, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
@@ -502,8 +521,18 @@ __global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in,
 struct TileCfg {
     int tx, ty;
 };
-constexpr TileCfg kTiles[] = {{0, 0}, {64, 4}, {64, 2}, {32, 8}};
+constexpr TileCfg kTiles[] = {{0, 0}, {64, 4}, {64, 2}, {32, 8}, {64, 8}, {128, 4}, {128, 2}};
+
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+// Workgroup-to-XCD remapping of tiles (FD6_XCD_REMAP=0 disables it).
+int xcd_remap() {
+    static const int v = [] {
+        const char* e = getenv("FD6_XCD_REMAP");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    return v;
+}
 
 template <typename T, typename TW, int TX, int TY>
 hipError_t launch_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
@@ -521,18 +550,19 @@ hipError_t launch_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW
     nch = (g.nz + zlen - 1) / zlen;
     const dim3 grid((unsigned)(tiles * nch));
     const dim3 block(TX * TY);
+    const int rm = xcd_remap();
     switch (s) {
     case 1:
         hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 1>), grid, block, 0, st, g, in, out,
-                           w, c, rk, ntx, nty, zlen);
+                           w, c, rk, ntx, nty, zlen, rm);
         break;
     case 2:
         hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 2>), grid, block, 0, st, g, in, out,
-                           w, c, rk, ntx, nty, zlen);
+                           w, c, rk, ntx, nty, zlen, rm);
         break;
     default:
         hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 3>), grid, block, 0, st, g, in, out,
-                           w, c, rk, ntx, nty, zlen);
+                           w, c, rk, ntx, nty, zlen, rm);
         break;
     }
     return hipGetLastError();
@@ -572,9 +602,14 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
     case 1: return launch_sweep<T, TW, 64, 4>(g, in, out, w, c, rk, s, st);
     case 2: return launch_sweep<T, TW, 64, 2>(g, in, out, w, c, rk, s, st);
     case 3: return launch_sweep<T, TW, 32, 8>(g, in, out, w, c, rk, s, st);
+    case 4: return launch_sweep<T, TW, 64, 8>(g, in, out, w, c, rk, s, st);
+    case 5: return launch_sweep<T, TW, 128, 4>(g, in, out, w, c, rk, s, st);
+    case 6: return launch_sweep<T, TW, 128, 2>(g, in, out, w, c, rk, s, st);
     default: return hipErrorInvalidValue;
     }
 }
+
+bool substep55_reads_ghosts(int tile) { return tile == 0; }
 
 template hipError_t launch_substep55<double, double>(const Geom&, Fields4<double>,
                                                      Fields4<double>, Fields4<double>,

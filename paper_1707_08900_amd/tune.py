@@ -1,0 +1,77 @@
+"""Autotuner for the 55-point substep kernel shape.
+
+Times every kernel shape the library offers (fd6_tile_count) on the caller's
+own box with HIP events, keeps the fastest, and caches the choice in a JSON
+file keyed by grid shape, precision, variant and device name (path from
+FD6_TUNE_CACHE, default ~/.cache/fd6_tune.json).  Tuning runs real steps, so
+it advances the box's state: call it before init_fields of the actual run,
+or re-initialise afterwards.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Optional
+
+import torch
+
+from . import Box, tile_count
+
+
+def _cache_path() -> str:
+    return os.environ.get("FD6_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "fd6_tune.json"))
+
+
+def _key(box: Box) -> str:
+    name = torch.cuda.get_device_name(box.device)
+    nz, ny, nx = box.shape
+    return f"{name}|{nx}x{ny}x{nz}|{box.precision}|{box.variant}"
+
+
+def _load() -> Dict[str, dict]:
+    try:
+        with open(_cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_tile(box: Box, tile: int, steps: int = 3) -> float:
+    """Milliseconds per full RK3 step with the given kernel shape."""
+    box.set_tile(tile)
+    box.step(1)  # warm-up (code object load, caches)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(box.stream)
+    box.step(steps)
+    e1.record(box.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def tune(box: Box, steps: int = 3, use_cache: bool = True,
+         candidates: Optional[list] = None) -> dict:
+    """Pick the fastest kernel shape for this box; returns {tile, ms, timings}."""
+    key = _key(box)
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        box.set_tile(cache[key]["tile"])
+        return cache[key]
+    if box.variant != "55p":
+        return {"tile": 0, "ms": None, "timings": {}}
+    tiles = candidates if candidates is not None else list(range(1, tile_count()))
+    timings = {t: time_tile(box, t, steps) for t in tiles}
+    best = min(timings, key=timings.get)
+    box.set_tile(best)
+    result = {"tile": best, "ms": timings[best], "timings": {str(k): v for k, v in timings.items()}}
+    if use_cache:
+        cache[key] = result
+        path = _cache_path()
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return result
