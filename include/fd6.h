@@ -178,6 +178,59 @@ int fd6_get_timing(fd6_box *box, double *kernel_ms, int64_t *kernel_launches, do
 /* Text of the last error on this handle ("" if none). */
 const char *fd6_last_error(const fd6_box *box);
 
+/* ---------------------------------------------------------------------------
+ * Batched ensemble: n independent periodic boxes of possibly different sizes
+ * and parameters, all with the same precision and the 55-point method,
+ * advanced together.  Each substep is ONE persistent kernel launch over the
+ * tile-chunks of every box (longest first); a full step (3 substeps) is
+ * replayed from a captured HIP graph.  Per-box geometry, pointers,
+ * coefficients and time steps live in device memory inside the workspace.
+ * Per grid point the arithmetic is that of the single-box z-sweep kernel with
+ * the same tile shape, so each box's result equals a single-box run bit for
+ * bit.  Conventions (status codes, host layout, workspace ownership, stream)
+ * as for fd6_box.
+ * ------------------------------------------------------------------------- */
+typedef struct fd6_batch fd6_batch;
+
+/* Workspace for n boxes described by descs[0..n-1] (same precision; variant
+ * FD6_55P, else FD6_EUNSUPPORTED). */
+int fd6_batch_workspace_bytes(int32_t n, const fd6_desc *descs, size_t *bytes);
+
+/* Create the ensemble in the caller's workspace (256-byte aligned). */
+int fd6_batch_create(int32_t n, const fd6_desc *descs, void *d_workspace, size_t bytes,
+                     void *stream, fd6_batch **out);
+int fd6_batch_destroy(fd6_batch *batch);
+
+/* Parameters of every box: per_box[0..n-1], validated like fd6_set_params.
+ * Uploads the device descriptors (synchronises). */
+int fd6_batch_set_params(fd6_batch *batch, const fd6_params *per_box);
+
+/* State of box `box` from host FP64 arrays; resets its RK3 register. */
+int fd6_batch_init_fields(fd6_batch *batch, int32_t box, const double *lnrho, const double *ux,
+                          const double *uy, const double *uz);
+
+/* Kernel shape (1 .. fd6_tile_count()-1, a z-sweep shape) and z-chunk length
+ * of the work items (0 = whole box); rebuilds the work list and drops any
+ * captured graph.  Default: shape 3 (32 x 8), whole boxes. */
+int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
+
+/* enable != 0 (default): steps replay a captured graph of the 3 substeps;
+ * 0: the same kernels are launched directly. */
+int fd6_batch_set_graph(fd6_batch *batch, int32_t enable);
+
+/* Advance every box by nsteps full RK3 steps.  Asynchronous. */
+int fd6_batch_step(fd6_batch *batch, int32_t nsteps);
+
+/* State of box `box` to host FP64 arrays.  Synchronises. */
+int fd6_batch_get_fields(fd6_batch *batch, int32_t box, double *lnrho, double *ux, double *uy,
+                         double *uz);
+
+/* FP64 diagnostics of every box into per_box[0..n-1] (as fd6_reduce).
+ * Synchronises; FD6_ENONFINITE if any box holds a non-finite value. */
+int fd6_batch_reduce(fd6_batch *batch, fd6_reductions *per_box);
+
+const char *fd6_batch_last_error(const fd6_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

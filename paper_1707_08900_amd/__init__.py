@@ -30,7 +30,10 @@ ABI_SYMBOLS = (
     "fd6_set_stream", "fd6_set_params", "fd6_init_fields", "fd6_init_fields_device",
     "fd6_rk3_step", "fd6_rk3_step_reduce", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
     "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_timing", "fd6_get_timing",
-    "fd6_last_error",
+    "fd6_last_error", "fd6_batch_workspace_bytes", "fd6_batch_create", "fd6_batch_destroy",
+    "fd6_batch_set_params", "fd6_batch_init_fields", "fd6_batch_set_schedule",
+    "fd6_batch_set_graph", "fd6_batch_step", "fd6_batch_get_fields", "fd6_batch_reduce",
+    "fd6_batch_last_error",
 )
 
 
@@ -84,6 +87,19 @@ def _declare(lib):
         "fd6_tile_count": (I, []),
         "fd6_set_tile": (I, [P, ctypes.c_int32]),
         "fd6_last_error": (ctypes.c_char_p, [P]),
+        "fd6_batch_workspace_bytes": (I, [ctypes.c_int32, ctypes.POINTER(Fd6Desc),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+        "fd6_batch_create": (I, [ctypes.c_int32, ctypes.POINTER(Fd6Desc), P, ctypes.c_size_t, P,
+                                 ctypes.POINTER(P)]),
+        "fd6_batch_destroy": (I, [P]),
+        "fd6_batch_set_params": (I, [P, ctypes.POINTER(Fd6Params)]),
+        "fd6_batch_init_fields": (I, [P, ctypes.c_int32, D, D, D, D]),
+        "fd6_batch_set_schedule": (I, [P, ctypes.c_int32, ctypes.c_int32]),
+        "fd6_batch_set_graph": (I, [P, ctypes.c_int32]),
+        "fd6_batch_step": (I, [P, ctypes.c_int32]),
+        "fd6_batch_get_fields": (I, [P, ctypes.c_int32, D, D, D, D]),
+        "fd6_batch_reduce": (I, [P, ctypes.POINTER(Fd6Reductions)]),
+        "fd6_batch_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -244,6 +260,89 @@ class Box:
 
     def set_tile(self, tile: int):
         self._check(self.lib.fd6_set_tile(self.h, int(tile)), "fd6_set_tile")
+
+
+class Batch:
+    """An ensemble of independent periodic boxes advanced together on the GPU
+    (one persistent launch per substep, a captured graph per step)."""
+
+    def __init__(self, shapes, precision: str = "fp32", device: str = "cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("paper_1707_08900_amd needs a ROCm GPU (gfx950); none is visible")
+        self.lib = library()
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.n = len(self.shapes)
+        self.precision = precision
+        self.device = torch.device(device)
+        arr = (Fd6Desc * self.n)()
+        for i, (nz, ny, nx) in enumerate(self.shapes):
+            arr[i] = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS["55p"], 0)
+        self._descs = arr
+        need = ctypes.c_size_t()
+        rc = self.lib.fd6_batch_workspace_bytes(self.n, arr, ctypes.byref(need))
+        if rc != 0:
+            raise Fd6Error(rc, "fd6_batch_workspace_bytes")
+        self._ws = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self._ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.fd6_batch_create(self.n, arr, ctypes.c_void_p(aligned), need.value,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise Fd6Error(rc, "fd6_batch_create")
+        self.h = h
+
+    def _check(self, rc, what):
+        if rc != 0:
+            detail = (self.lib.fd6_batch_last_error(self.h) or b"").decode()
+            raise Fd6Error(rc, what, detail)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fd6_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        """params: sequence of (nu, cs, dx, dy, dz, dt), one per box."""
+        arr = (Fd6Params * self.n)(*[Fd6Params(*p) for p in params])
+        self._check(self.lib.fd6_batch_set_params(self.h, arr), "fd6_batch_set_params")
+
+    def init_fields(self, box: int, fields):
+        arrs = [np.ascontiguousarray(f, dtype=np.float64) for f in fields]
+        for a in arrs:
+            assert a.shape == self.shapes[box]
+        self._check(self.lib.fd6_batch_init_fields(self.h, box, *[_dptr(a) for a in arrs]),
+                    "fd6_batch_init_fields")
+
+    def set_schedule(self, tile: int, zchunk: int = 0):
+        self._check(self.lib.fd6_batch_set_schedule(self.h, tile, zchunk), "fd6_batch_set_schedule")
+
+    def set_graph(self, enable: bool):
+        self._check(self.lib.fd6_batch_set_graph(self.h, 1 if enable else 0), "fd6_batch_set_graph")
+
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.fd6_batch_step(self.h, int(nsteps)), "fd6_batch_step")
+
+    def get_fields(self, box: int):
+        out = [np.empty(self.shapes[box]) for _ in range(4)]
+        self._check(self.lib.fd6_batch_get_fields(self.h, box, *[_dptr(a) for a in out]),
+                    "fd6_batch_get_fields")
+        return out
+
+    def reduce(self):
+        arr = (Fd6Reductions * self.n)()
+        rc = self.lib.fd6_batch_reduce(self.h, arr)
+        if rc not in (0, -5):
+            self._check(rc, "fd6_batch_reduce")
+        return [{"mass": r.mass, "kinetic_energy": r.kinetic_energy, "sum_lnrho": r.sum_lnrho,
+                 "umax": r.umax, "nonfinite": int(r.nonfinite)} for r in arr]
 
 
 def tile_count() -> int:

@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <algorithm>
+#include <array>
 #include <new>
 #include <string>
 #include <utility>
@@ -51,6 +53,53 @@ struct fd6_box {
         for (auto& p : ev_kernel) ev_pool.push_back(p.first), ev_pool.push_back(p.second);
         for (auto& p : ev_ghost) ev_pool.push_back(p.first), ev_pool.push_back(p.second);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    }
+};
+
+// Ensemble of independent boxes advanced together (batched form).
+struct fd6_batch {
+    int n = 0;
+    int precision = 0;
+    int tile = 3;
+    int zchunk = 0;  // 0: whole box per work item
+    bool use_graph = true;
+    hipStream_t stream = nullptr;   // caller's stream (graph launches, transfers)
+    hipStream_t cap = nullptr;      // private stream used only for graph capture
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t tsize = 0, wsize = 0;
+    std::vector<fd6_desc> desc;
+    std::vector<Geom> geom;
+    std::vector<fd6_params> params;
+    std::vector<bool> have_fields;
+    std::vector<std::array<void*, 4>> st[2], w;
+    bool have_params = false;
+    int parity = 0;              // state set holding the current state (all boxes)
+    void* boxes_dev = nullptr;   // BatchBox<T, TW>[n]
+    size_t box_bytes = 0;
+    BatchItem* items_dev = nullptr;
+    long long items_cap = 0;
+    int nitems = 0, grid = 0;
+    double* partials = nullptr;
+    double* results = nullptr;   // n x kReduceSlots
+    double* staging = nullptr;
+    long long staging_elems = 0;
+    bool graph_ok = false;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    std::string err;
+    void drop_graphs() {
+        for (int i = 0; i < 2; ++i) {
+            if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+            exec[i] = nullptr;
+            graph[i] = nullptr;
+        }
+        graph_ok = false;
+    }
+    ~fd6_batch() {
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
@@ -140,7 +189,8 @@ int make_plan(const fd6_desc* d, Plan* p) {
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-int hip_fail(fd6_box* b, hipError_t e, const char* what) {
+template <typename H>
+int hip_fail(H* b, hipError_t e, const char* what) {
     b->err = std::string(what) + ": " + hipGetErrorString(e);
     return FD6_EHIP;
 }
@@ -425,8 +475,8 @@ int dispatch(fd6_box* b, F&& f) {
     }
 }
 
-template <typename F>
-int guarded(fd6_box* b, F&& f) {
+template <typename H, typename F>
+int guarded(H* b, F&& f) {
     try {
         return f();
     } catch (const std::bad_alloc&) {
@@ -442,6 +492,247 @@ int guarded(fd6_box* b, F&& f) {
 }
 
 bool ready(fd6_box* b) { return b->have_params && b->have_fields; }
+
+
+// ---------------------------------------------------------------------------
+// Batched ensemble
+// ---------------------------------------------------------------------------
+
+struct BatchPlan {
+    std::vector<Plan> box;
+    std::vector<size_t> base;  // workspace offset of each box's fields
+    size_t off_boxes, off_items, off_partials, off_results, off_staging, total;
+    size_t box_bytes;
+    long long items_cap, staging_elems;
+};
+
+size_t batch_box_bytes(int prec) {
+    switch (prec) {
+    case FD6_FP64: return sizeof(BatchBox<double, double>);
+    case FD6_FP32: return sizeof(BatchBox<float, float>);
+    default: return sizeof(BatchBox<float, double>);
+    }
+}
+
+int make_batch_plan(int n, const fd6_desc* d, BatchPlan* bp) {
+    if (n < 1 || n > 65536 || !d) return FD6_EINVAL;
+    bp->box.resize(n);
+    bp->base.resize(n);
+    size_t off = 0;
+    long long items = 0, stag = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = make_plan(&d[i], &bp->box[i]);
+        if (rc) return rc;
+        if (d[i].precision != d[0].precision) return FD6_EINVAL;
+        if (d[i].variant != FD6_55P) return FD6_EUNSUPPORTED;
+        bp->base[i] = off;
+        // this box's state and w fields (the per-box plan puts them first)
+        off += bp->box[i].off_div;
+        // work items of the smallest tile (32 x 2) and z chunks of >= 8 planes
+        items += (long long)((d[i].nx + 31) / 32) * ((d[i].ny + 1) / 2) * ((d[i].nz + 7) / 8);
+        const long long pc = (long long)d[i].nx * d[i].ny;
+        long long st = std::min<long long>(pc * d[i].nz, std::max<long long>(pc, 1LL << 22));
+        stag = std::max(stag, st);
+    }
+    bp->box_bytes = batch_box_bytes(d[0].precision);
+    bp->off_boxes = off;
+    off += round_up(bp->box_bytes * n, kAlign);
+    bp->items_cap = items;
+    bp->off_items = off;
+    off += round_up(sizeof(BatchItem) * items, kAlign);
+    bp->off_partials = off;
+    off += round_up((size_t)kReduceBlocks * kReduceSlots * sizeof(double), kAlign);
+    bp->off_results = off;
+    off += round_up((size_t)n * kReduceSlots * sizeof(double), kAlign);
+    bp->staging_elems = stag;
+    bp->off_staging = off;
+    off += round_up((size_t)stag * sizeof(double), kAlign);
+    bp->total = off;
+    return FD6_OK;
+}
+
+// Per-box descriptors (geometry, both state sets, w, coefficients, dt).
+template <typename T, typename TW>
+int upload_boxes(fd6_batch* b) {
+    std::vector<BatchBox<T, TW>> h(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        h[i].g = b->geom[i];
+        h[i].st[0] = fields_of<T>(b->st[0][i].data());
+        h[i].st[1] = fields_of<T>(b->st[1][i].data());
+        h[i].w = fields_of<TW>(b->w[i].data());
+        h[i].cf = make_coef<T>(b->params[i]);
+        h[i].dt = TW(b->params[i].dt);
+    }
+    HIPCHK(b, hipMemcpyAsync(b->boxes_dev, h.data(), sizeof(BatchBox<T, TW>) * b->n,
+                             hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    return FD6_OK;
+}
+
+// Work list for the current kernel shape: all tile-chunks, longest first
+// (then box, then z, y, x order so that neighbouring tiles stay adjacent).
+template <typename T, typename TW>
+int build_items(fd6_batch* b) {
+    int tx = 0, ty = 0;
+    if (substep55_tile_dims(b->tile, &tx, &ty)) return FD6_EINVAL;
+    std::vector<BatchItem> it;
+    std::vector<long long> cost;
+    for (int i = 0; i < b->n; ++i) {
+        const Geom& g = b->geom[i];
+        const int zl = b->zchunk > 0 ? std::min(b->zchunk, g.nz) : g.nz;
+        for (int zb = 0; zb < g.nz; zb += zl)
+            for (int y0 = 0; y0 < g.ny; y0 += ty)
+                for (int x0 = 0; x0 < g.nx; x0 += tx) {
+                    it.push_back(BatchItem{i, x0, y0, zb, std::min(zb + zl, g.nz)});
+                    cost.push_back((long long)(std::min(zb + zl, g.nz) - zb + 2 * kR));
+                }
+    }
+    if ((long long)it.size() > b->items_cap) return FD6_EUNSUPPORTED;
+    std::vector<int> order(it.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<BatchItem> sorted(it.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = it[order[k]];
+    b->nitems = (int)sorted.size();
+    HIPCHK(b, hipMemcpyAsync(b->items_dev, sorted.data(), sizeof(BatchItem) * sorted.size(),
+                             hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    // persistent grid: every resident workgroup, a multiple of the 8 XCDs
+    int dev = 0, cus = 0;
+    HIPCHK(b, hipGetDevice(&dev));
+    HIPCHK(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    long long gsz = (long long)cus * batch55_blocks_per_cu<T, TW>(b->tile);
+    gsz = std::min<long long>(gsz, b->nitems);
+    if (gsz >= 8) gsz = gsz / 8 * 8;
+    b->grid = (int)std::max<long long>(gsz, 1);
+    b->drop_graphs();
+    return FD6_OK;
+}
+
+template <typename T, typename TW>
+int batch_substeps(fd6_batch* b, hipStream_t st, int parity) {
+    for (int s = 0; s < 3; ++s) {
+        HIPCHK(b, (launch_batch55<T, TW>(static_cast<const BatchBox<T, TW>*>(b->boxes_dev),
+                                         b->items_dev, b->nitems, b->grid, parity, s + 1,
+                                         b->tile, TW(kAlpha[s]), TW(kBeta[s]), st)));
+        parity ^= 1;
+    }
+    return FD6_OK;
+}
+
+// One graph per starting parity: substeps 1-3 of a full step.
+template <typename T, typename TW>
+int build_graphs(fd6_batch* b) {
+    b->drop_graphs();
+    if (!b->cap) HIPCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    for (int p = 0; p < 2; ++p) {
+        HIPCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        int rc = batch_substeps<T, TW>(b, b->cap, p);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap, &gr);
+        if (rc) return rc;
+        if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
+        b->graph[p] = gr;
+        HIPCHK(b, hipGraphInstantiate(&b->exec[p], gr, nullptr, nullptr, 0));
+    }
+    b->graph_ok = true;
+    return FD6_OK;
+}
+
+template <typename T, typename TW>
+int batch_steps(fd6_batch* b, int nsteps) {
+    if (b->nitems == 0) {
+        int rc = build_items<T, TW>(b);
+        if (rc) return rc;
+    }
+    if (b->use_graph && !b->graph_ok) {
+        int rc = build_graphs<T, TW>(b);
+        if (rc) return rc;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        if (b->use_graph) {
+            HIPCHK(b, hipGraphLaunch(b->exec[b->parity], b->stream));
+        } else {
+            int rc = batch_substeps<T, TW>(b, b->stream, b->parity);
+            if (rc) return rc;
+        }
+        b->parity ^= 1;
+    }
+    return FD6_OK;
+}
+
+template <typename F>
+int batch_dispatch(fd6_batch* b, F&& f) {
+    switch (b->precision) {
+    case FD6_FP64: return f((double*)nullptr, (double*)nullptr);
+    case FD6_FP32: return f((float*)nullptr, (float*)nullptr);
+    default: return f((float*)nullptr, (double*)nullptr);
+    }
+}
+
+template <typename T>
+int batch_import(fd6_batch* b, int i, const double* const src[4]) {
+    const Geom& g = b->geom[i];
+    const long long plane_c = (long long)g.nx * g.ny;
+    const int chunk = (int)std::max<long long>(1, b->staging_elems / plane_c);
+    for (int q = 0; q < 4; ++q) {
+        T* dst = static_cast<T*>(b->st[b->parity][i][q]);
+        for (int z = 0; z < g.nz; z += chunk) {
+            const int np = (z + chunk <= g.nz) ? chunk : g.nz - z;
+            HIPCHK(b, hipMemcpyAsync(b->staging, src[q] + (long long)z * plane_c,
+                                     (size_t)np * plane_c * sizeof(double), hipMemcpyHostToDevice,
+                                     b->stream));
+            HIPCHK(b, launch_import<T>(g, b->staging, dst, z, np, b->stream));
+            HIPCHK(b, hipStreamSynchronize(b->stream));
+        }
+    }
+    return FD6_OK;
+}
+
+template <typename T>
+int batch_export(fd6_batch* b, int i, double* const dst[4]) {
+    const Geom& g = b->geom[i];
+    const long long plane_c = (long long)g.nx * g.ny;
+    const int chunk = (int)std::max<long long>(1, b->staging_elems / plane_c);
+    for (int q = 0; q < 4; ++q) {
+        const T* src = static_cast<const T*>(b->st[b->parity][i][q]);
+        for (int z = 0; z < g.nz; z += chunk) {
+            const int np = (z + chunk <= g.nz) ? chunk : g.nz - z;
+            HIPCHK(b, launch_export<T>(g, src, b->staging, z, np, b->stream));
+            HIPCHK(b, hipMemcpyAsync(dst[q] + (long long)z * plane_c, b->staging,
+                                     (size_t)np * plane_c * sizeof(double), hipMemcpyDeviceToHost,
+                                     b->stream));
+            HIPCHK(b, hipStreamSynchronize(b->stream));
+        }
+    }
+    return FD6_OK;
+}
+
+template <typename T>
+int batch_reduce(fd6_batch* b, fd6_reductions* out) {
+    for (int i = 0; i < b->n; ++i) {
+        const fd6_params& p = b->params[i];
+        HIPCHK(b, launch_reduce<T>(b->geom[i], fields_of<T>(b->st[b->parity][i].data()),
+                                   b->partials, b->results + (size_t)i * kReduceSlots,
+                                   p.dx * p.dy * p.dz, b->stream));
+    }
+    std::vector<double> h((size_t)b->n * kReduceSlots);
+    HIPCHK(b, hipMemcpyAsync(h.data(), b->results, h.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
+    bool bad = false;
+    for (int i = 0; i < b->n; ++i) {
+        const double* r = &h[(size_t)i * kReduceSlots];
+        out[i].mass = r[0];
+        out[i].kinetic_energy = r[1];
+        out[i].sum_lnrho = r[2];
+        out[i].umax = r[3];
+        out[i].nonfinite = (int64_t)r[4];
+        bad = bad || out[i].nonfinite > 0;
+    }
+    return bad ? FD6_ENONFINITE : FD6_OK;
+}
 
 }  // namespace
 
@@ -478,7 +769,7 @@ int fd6_create(const fd6_desc* desc, void* d_ws, size_t bytes, void* stream, fd6
     if (rc) return rc;
     if (((uintptr_t)d_ws) % kAlign != 0) return FD6_EINVAL;
     if (bytes < p.total) return FD6_ENOMEM;
-    return guarded(nullptr, [&]() -> int {
+    return guarded((fd6_box*)nullptr, [&]() -> int {
         fd6_box* b = new fd6_box();
         b->desc = *desc;
         b->geom = p.g;
@@ -688,5 +979,166 @@ int fd6_set_tile(fd6_box* b, int32_t tile) {
 }
 
 int fd6_tile_count(void) { return substep55_tile_count(); }
+
+int fd6_batch_workspace_bytes(int32_t n, const fd6_desc* descs, size_t* bytes) {
+    if (!bytes) return FD6_EINVAL;
+    BatchPlan bp;
+    int rc = make_batch_plan(n, descs, &bp);
+    if (rc) return rc;
+    *bytes = bp.total;
+    return FD6_OK;
+}
+
+int fd6_batch_create(int32_t n, const fd6_desc* descs, void* d_ws, size_t bytes, void* stream,
+                     fd6_batch** out) {
+    if (!out || !d_ws) return FD6_EINVAL;
+    BatchPlan bp;
+    int rc = make_batch_plan(n, descs, &bp);
+    if (rc) return rc;
+    if (((uintptr_t)d_ws) % kAlign != 0) return FD6_EINVAL;
+    if (bytes < bp.total) return FD6_ENOMEM;
+    return guarded((fd6_batch*)nullptr, [&]() -> int {
+        fd6_batch* b = new fd6_batch();
+        b->n = n;
+        b->precision = descs[0].precision;
+        b->stream = static_cast<hipStream_t>(stream);
+        b->ws = static_cast<char*>(d_ws);
+        b->ws_bytes = bytes;
+        b->desc.assign(descs, descs + n);
+        b->geom.resize(n);
+        b->params.resize(n);
+        b->have_fields.assign(n, false);
+        b->st[0].resize(n);
+        b->st[1].resize(n);
+        b->w.resize(n);
+        for (int i = 0; i < n; ++i) {
+            const Plan& p = bp.box[i];
+            b->geom[i] = p.g;
+            char* base = b->ws + bp.base[i];
+            for (int s = 0; s < 2; ++s)
+                for (int q = 0; q < 4; ++q) b->st[s][i][q] = base + p.off_state[s][q];
+            for (int q = 0; q < 4; ++q) b->w[i][q] = base + p.off_w[q];
+        }
+        b->tsize = bp.box[0].tsize;
+        b->wsize = bp.box[0].wsize;
+        b->boxes_dev = b->ws + bp.off_boxes;
+        b->box_bytes = bp.box_bytes;
+        b->items_dev = reinterpret_cast<BatchItem*>(b->ws + bp.off_items);
+        b->items_cap = bp.items_cap;
+        b->partials = reinterpret_cast<double*>(b->ws + bp.off_partials);
+        b->results = reinterpret_cast<double*>(b->ws + bp.off_results);
+        b->staging = reinterpret_cast<double*>(b->ws + bp.off_staging);
+        b->staging_elems = bp.staging_elems;
+        *out = b;
+        return FD6_OK;
+    });
+}
+
+int fd6_batch_destroy(fd6_batch* b) {
+    delete b;
+    return FD6_OK;
+}
+
+int fd6_batch_set_params(fd6_batch* b, const fd6_params* per_box) {
+    if (!b || !per_box) return FD6_EINVAL;
+    for (int i = 0; i < b->n; ++i) {
+        const fd6_params* p = &per_box[i];
+        if (!finite_nonneg(p->nu) || !finite_nonneg(p->cs) || !finite_pos(p->dx) ||
+            !finite_pos(p->dy) || !finite_pos(p->dz) || !finite_pos(p->dt))
+            return FD6_EINVAL;
+    }
+    return guarded(b, [&]() -> int {
+        b->params.assign(per_box, per_box + b->n);
+        b->have_params = true;
+        return batch_dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            return upload_boxes<T, TW>(b);
+        });
+    });
+}
+
+int fd6_batch_init_fields(fd6_batch* b, int32_t box, const double* lnrho, const double* ux,
+                          const double* uy, const double* uz) {
+    if (!b || box < 0 || box >= b->n || !lnrho || !ux || !uy || !uz) return FD6_EINVAL;
+    return guarded(b, [&]() -> int {
+        const double* src[4] = {lnrho, ux, uy, uz};
+        int rc = batch_dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            int r = batch_import<T>(b, box, src);
+            if (r) return r;
+            HIPCHK(b, launch_zero_w<TW>(b->geom[box], fields_of<TW>(b->w[box].data()), b->stream));
+            HIPCHK(b, hipStreamSynchronize(b->stream));
+            return FD6_OK;
+        });
+        if (rc) return rc;
+        b->have_fields[box] = true;
+        return FD6_OK;
+    });
+}
+
+int fd6_batch_set_schedule(fd6_batch* b, int32_t tile, int32_t zchunk) {
+    int tx, ty;
+    if (!b || zchunk < 0 || substep55_tile_dims(tile, &tx, &ty)) return FD6_EINVAL;
+    return guarded(b, [&]() -> int {
+        b->tile = tile;
+        b->zchunk = zchunk;
+        return batch_dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            return build_items<T, TW>(b);
+        });
+    });
+}
+
+int fd6_batch_set_graph(fd6_batch* b, int32_t enable) {
+    if (!b) return FD6_EINVAL;
+    b->use_graph = enable != 0;
+    return FD6_OK;
+}
+
+int fd6_batch_step(fd6_batch* b, int32_t nsteps) {
+    if (!b || nsteps < 0) return FD6_EINVAL;
+    if (!b->have_params) return FD6_ESTATE;
+    for (int i = 0; i < b->n; ++i)
+        if (!b->have_fields[i]) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        return batch_dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            return batch_steps<T, TW>(b, nsteps);
+        });
+    });
+}
+
+int fd6_batch_get_fields(fd6_batch* b, int32_t box, double* lnrho, double* ux, double* uy,
+                         double* uz) {
+    if (!b || box < 0 || box >= b->n || !lnrho || !ux || !uy || !uz) return FD6_EINVAL;
+    if (!b->have_fields[box]) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        double* dst[4] = {lnrho, ux, uy, uz};
+        return batch_dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return batch_export<T>(b, box, dst);
+        });
+    });
+}
+
+int fd6_batch_reduce(fd6_batch* b, fd6_reductions* per_box) {
+    if (!b || !per_box) return FD6_EINVAL;
+    if (!b->have_params) return FD6_ESTATE;
+    for (int i = 0; i < b->n; ++i)
+        if (!b->have_fields[i]) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        return batch_dispatch(b, [&](auto* t, auto*) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            return batch_reduce<T>(b, per_box);
+        });
+    });
+}
+
+const char* fd6_batch_last_error(const fd6_batch* b) { return b ? b->err.c_str() : ""; }
+
 
 }  // extern "C"

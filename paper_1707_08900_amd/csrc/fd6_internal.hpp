@@ -101,6 +101,28 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
 // shapes resolve the periodic images in their loader instead).
 bool substep55_reads_ghosts(int tile);
 
+// Batched ensemble: per-box descriptor (device resident) and one tile-chunk
+// work item.
+template <typename T, typename TW>
+struct BatchBox {
+    Geom g;
+    Fields4<T> st[2];  // the two state sets; st[parity] is the substep input
+    Fields4<TW> w;
+    Coef<T> cf;
+    TW dt;
+};
+struct BatchItem {
+    int box, x0, y0, zb, ze;
+};
+// Tile extents of a z-sweep kernel shape (tile >= 1); -1 for other shapes.
+int substep55_tile_dims(int tile, int* tx, int* ty);
+template <typename T, typename TW>
+hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                          int grid, int parity, int s, int tile, TW alpha, TW beta,
+                          hipStream_t st);
+template <typename T, typename TW>
+int batch55_blocks_per_cu(int tile);
+
 // 19-point method: pass 1 (divergence, partial update) and pass 2.
 template <typename T, typename TW>
 hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,

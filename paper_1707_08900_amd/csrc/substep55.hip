@@ -277,36 +277,89 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     const T* B2 = win + 2 * Sh::FS + C0;
     const T* B3 = win + 3 * Sh::FS + C0;
     constexpr int DS = PH & 3;  // first-derivative slot of plane p
+    constexpr T w2[3] = {T(270), T(-27), T(2)};
 
-    // lnrho: x and y first derivatives
+    // (A) what output p - 3 still needs from plane p: the centre values (top
+    // of the z queues) and the k = 3 terms of its xz / yz stencils.  The
+    // first contribution to output p + 3 (from the same differences) assigns.
     {
-        const T c = B0[0];
-        R.q[0][sl8(PH)] = c;
-        R.dd[DS][0] = cf.d1[0][0] * (B0[0 + 1] - B0[0 - 1]) +
-                      cf.d1[0][1] * (B0[0 + 2] - B0[0 - 2]) +
-                      cf.d1[0][2] * (B0[0 + 3] - B0[0 - 3]);
-        R.dd[DS][1] = cf.d1[1][0] * (B0[0 + W] - B0[0 - W]) +
-                      cf.d1[1][1] * (B0[0 + 2 * W] - B0[0 - 2 * W]) +
-                      cf.d1[1][2] * (B0[0 + 3 * W] - B0[0 - 3 * W]);
+        R.q[0][sl8(PH)] = B0[0];
+        R.q[1][sl8(PH)] = B1[0];
+        R.q[2][sl8(PH)] = B2[0];
+        R.q[3][sl8(PH)] = B3[0];
+        const T zs3[3] = {cf.mu[1] * (B3[3] - B3[-3]),                 // (1/3) Dxz uz
+                          cf.mu[2] * (B3[3 * W] - B3[-3 * W]),         // (1/3) Dyz uz
+                          cf.mu[1] * (B1[3] - B1[-3]) +                // (1/3) Dxz ux
+                              cf.mu[2] * (B2[3 * W] - B2[-3 * W])};    // + (1/3) Dyz uy
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            R.L[i][sl8(PH - 3)] += T(2) * zs3[i];
+            R.L[i][sl8(PH + 3)] = T(-2) * zs3[i];
+        }
     }
-    T lx, ly, lz;         // xy parts of nu (lap u_i + (1/3) d_i div u) at plane p
-    T zx[3], zy[3], zz[3];  // scaled x/y differences feeding the xz / yz terms
+
+    // (B) finish output plane o = p - 3 before the rest of plane p is formed,
+    // so the two working sets do not overlap in registers
+    if (outstep) {
+        T dz[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            dz[f] = cf.d1[2][0] * (R.q[f][sl8(PH - 2)] - R.q[f][sl8(PH - 4)]) +
+                    cf.d1[2][1] * (R.q[f][sl8(PH - 1)] - R.q[f][sl8(PH - 5)]) +
+                    cf.d1[2][2] * (R.q[f][sl8(PH)] - R.q[f][sl8(PH - 6)]);
+        T Lf[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int f = 1 + i;
+            const T rz = T(270) * (R.q[f][sl8(PH - 2)] + R.q[f][sl8(PH - 4)]) +
+                         T(-27) * (R.q[f][sl8(PH - 1)] + R.q[f][sl8(PH - 5)]) +
+                         T(2) * (R.q[f][sl8(PH)] + R.q[f][sl8(PH - 6)]) +
+                         T(-490) * R.q[f][sl8(PH - 3)];
+            Lf[i] = R.L[i][sl8(PH - 3)] + (i == 2 ? cf.sg4[2] : cf.sg[2]) * rz;
+        }
+        constexpr int DO = (PH + 1) & 3;  // slot of plane p - 3
+        const T gr[3] = {R.dd[DO][0], R.dd[DO][1], dz[0]};
+        const T J[3][3] = {{R.dd[DO][2], R.dd[DO][3], dz[1]},
+                           {R.dd[DO][4], R.dd[DO][5], dz[2]},
+                           {R.dd[DO][6], R.dd[DO][7], dz[3]}};
+        const T u[3] = {R.q[1][sl8(PH - 3)], R.q[2][sl8(PH - 3)], R.q[3][sl8(PH - 3)]};
+        T r[4];
+        assemble_rhs(u, gr, J, Lf, cf.nu, cf.cs2, r);
+        // ghost corner (-3, -3) of output plane o
+        const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv[f], rk);
+            bstore(v, plane_rsrc(out.f[f] + ocorner, X.plane_bytes), X.lane_o);
+            if constexpr (S != 3)
+                bstore(wv[f], plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes),
+                       X.lane_w);
+        }
+    }
+
+    // (C) the rest of plane p for this column: x / y first derivatives of the
+    // four fields (kept 3 planes), the xy part of the linear viscous term, and
+    // the k = 1, 2 terms of the xz / yz stencils of outputs p -+ k.
+    // lnrho
+    R.dd[DS][0] = cf.d1[0][0] * (B0[1] - B0[-1]) + cf.d1[0][1] * (B0[2] - B0[-2]) +
+                  cf.d1[0][2] * (B0[3] - B0[-3]);
+    R.dd[DS][1] = cf.d1[1][0] * (B0[W] - B0[-W]) + cf.d1[1][1] * (B0[2 * W] - B0[-2 * W]) +
+                  cf.d1[1][2] * (B0[3 * W] - B0[-3 * W]);
+    T lx, ly, lz;           // xy parts of nu (lap u_i + (1/3) d_i div u) at plane p
+    T zx[2], zy[2], zz[2];  // scaled k = 1, 2 differences feeding the xz / yz terms
     // ux
     {
         const T c = B1[0];
-        R.q[1][sl8(PH)] = c;
         T a[3], b[3];
         T rx = T(0), ry = T(0), m = T(0);
-        constexpr T w2[3] = {T(270), T(-27), T(2)};
 #pragma unroll
         for (int k = 1; k <= 3; ++k) {
-            const T xp = B1[0 + k], xm = B1[0 - k], yp = B1[0 + k * W], ym = B1[0 - k * W];
+            const T xp = B1[k], xm = B1[-k], yp = B1[k * W], ym = B1[-k * W];
             a[k - 1] = xp - xm;
             b[k - 1] = yp - ym;
             rx += w2[k - 1] * (xp + xm);
             ry += w2[k - 1] * (yp + ym);
-            const T t = (B1[0 + k * W + k] - B1[0 + k * W - k]) +
-                        (B1[0 - k * W - k] - B1[0 - k * W + k]);
+            const T t = (B1[k * W + k] - B1[k * W - k]) + (B1[-k * W - k] - B1[-k * W + k]);
             m += w2[k - 1] * t;
         }
         R.dd[DS][2] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
@@ -314,24 +367,21 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         lx = cf.kxy[0] * c + cf.sg4[0] * rx + cf.sg[1] * ry;  // (4/3) D2x + D2y
         ly = cf.mu[0] * m;                                     // (1/3) Dxy ux
 #pragma unroll
-        for (int k = 0; k < 3; ++k) zz[k] = cf.mu[1] * a[k];   // (1/3) Dxz ux
+        for (int k = 0; k < 2; ++k) zz[k] = cf.mu[1] * a[k];   // (1/3) Dxz ux
     }
     // uy
     {
         const T c = B2[0];
-        R.q[2][sl8(PH)] = c;
         T a[3], b[3];
         T rx = T(0), ry = T(0), m = T(0);
-        constexpr T w2[3] = {T(270), T(-27), T(2)};
 #pragma unroll
         for (int k = 1; k <= 3; ++k) {
-            const T xp = B2[0 + k], xm = B2[0 - k], yp = B2[0 + k * W], ym = B2[0 - k * W];
+            const T xp = B2[k], xm = B2[-k], yp = B2[k * W], ym = B2[-k * W];
             a[k - 1] = xp - xm;
             b[k - 1] = yp - ym;
             rx += w2[k - 1] * (xp + xm);
             ry += w2[k - 1] * (yp + ym);
-            const T t = (B2[0 + k * W + k] - B2[0 + k * W - k]) +
-                        (B2[0 - k * W - k] - B2[0 - k * W + k]);
+            const T t = (B2[k * W + k] - B2[k * W - k]) + (B2[-k * W - k] - B2[-k * W + k]);
             m += w2[k - 1] * t;
         }
         R.dd[DS][4] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
@@ -339,18 +389,16 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         ly += cf.kxy[1] * c + cf.sg[0] * rx + cf.sg4[1] * ry;  // D2x + (4/3) D2y
         lx += cf.mu[0] * m;                                     // (1/3) Dxy uy
 #pragma unroll
-        for (int k = 0; k < 3; ++k) zz[k] += cf.mu[2] * b[k];   // (1/3) Dyz uy
+        for (int k = 0; k < 2; ++k) zz[k] += cf.mu[2] * b[k];   // (1/3) Dyz uy
     }
     // uz
     {
         const T c = B3[0];
-        R.q[3][sl8(PH)] = c;
         T a[3], b[3];
         T rx = T(0), ry = T(0);
-        constexpr T w2[3] = {T(270), T(-27), T(2)};
 #pragma unroll
         for (int k = 1; k <= 3; ++k) {
-            const T xp = B3[0 + k], xm = B3[0 - k], yp = B3[0 + k * W], ym = B3[0 - k * W];
+            const T xp = B3[k], xm = B3[-k], yp = B3[k * W], ym = B3[-k * W];
             a[k - 1] = xp - xm;
             b[k - 1] = yp - ym;
             rx += w2[k - 1] * (xp + xm);
@@ -360,91 +408,40 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         R.dd[DS][7] = cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2];
         lz = cf.kxy[2] * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 2; ++k) {
             zx[k] = cf.mu[1] * a[k];  // (1/3) Dxz uz
-            zy[k] = cf.mu[2] * b[k];  // (1/3) Dyz uz
+            zy[k] = cf.mu[2] * b[k];  // (1/3) Dyz uy
         }
     }
 
     // Scatter: the bidiagonal xz / yz stencil at output z is
     // sum_k c_k [A_k(z + k) - A_k(z - k)], so plane p adds +c_k A_k to the
-    // pending output p - k and -c_k A_k to p + k (c = 270, -27, 2).  The
-    // first contribution an output receives (from p = z - 3) assigns.
+    // pending output p - k and -c_k A_k to p + k (c = 270, -27, 2); the k = 3
+    // terms were added in (A).
     {
         const T* zs[3] = {zx, zy, zz};
         const T lc[3] = {lx, ly, lz};
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            R.L[i][sl8(PH + 3)] = T(-2) * zs[i][2];
             R.L[i][sl8(PH + 2)] += T(27) * zs[i][1];
             R.L[i][sl8(PH + 1)] += T(-270) * zs[i][0];
             R.L[i][sl8(PH)] += lc[i];
             R.L[i][sl8(PH - 1)] += T(270) * zs[i][0];
             R.L[i][sl8(PH - 2)] += T(-27) * zs[i][1];
-            R.L[i][sl8(PH - 3)] += T(2) * zs[i][2];
         }
-    }
-
-    if (!outstep) return;
-
-    // ---- finish output plane o = p - 3 ----
-    T dz[4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-        dz[f] = cf.d1[2][0] * (R.q[f][sl8(PH - 2)] - R.q[f][sl8(PH - 4)]) +
-                cf.d1[2][1] * (R.q[f][sl8(PH - 1)] - R.q[f][sl8(PH - 5)]) +
-                cf.d1[2][2] * (R.q[f][sl8(PH)] - R.q[f][sl8(PH - 6)]);
-    T Lf[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int f = 1 + i;
-        const T rz = T(270) * (R.q[f][sl8(PH - 2)] + R.q[f][sl8(PH - 4)]) +
-                     T(-27) * (R.q[f][sl8(PH - 1)] + R.q[f][sl8(PH - 5)]) +
-                     T(2) * (R.q[f][sl8(PH)] + R.q[f][sl8(PH - 6)]) +
-                     T(-490) * R.q[f][sl8(PH - 3)];
-        Lf[i] = R.L[i][sl8(PH - 3)] + (i == 2 ? cf.sg4[2] : cf.sg[2]) * rz;
-    }
-    constexpr int DO = (PH + 1) & 3;  // slot of plane p - 3
-    const T gr[3] = {R.dd[DO][0], R.dd[DO][1], dz[0]};
-    const T J[3][3] = {{R.dd[DO][2], R.dd[DO][3], dz[1]},
-                       {R.dd[DO][4], R.dd[DO][5], dz[2]},
-                       {R.dd[DO][6], R.dd[DO][7], dz[3]}};
-    const T u[3] = {R.q[1][sl8(PH - 3)], R.q[2][sl8(PH - 3)], R.q[3][sl8(PH - 3)]};
-    T r[4];
-    assemble_rhs(u, gr, J, Lf, cf.nu, cf.cs2, r);
-    // ghost corner (-3, -3) of output plane o
-    const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv[f], rk);
-        bstore(v, plane_rsrc(out.f[f] + ocorner, X.plane_bytes), X.lane_o);
-        if constexpr (S != 3)
-            bstore(wv[f], plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes), X.lane_w);
     }
 }
 
+// One tile-chunk: columns [x0, x0 + TX) x [y0, y0 + TY) of the box, output
+// planes [zb, ze).  Every thread of the workgroup calls it with the same
+// arguments.
 template <typename T, typename TW, int TX, int TY, int S>
-__global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out,
-                                                          Fields4<TW> w, Coef<T> cf,
-                                                          RKCoef<TW> rk, int ntx, int nty,
-                                                          int zlen, int remap) {
+__device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
+                                           const Fields4<T>& out, const Fields4<TW>& w,
+                                           const Coef<T>& cf, const RKCoef<TW>& rk, int x0,
+                                           int y0, int zb, int ze, T* lds) {
     using Sh = SweepShape<T, TX, TY>;
     constexpr int NH = Sh::NH;
-    __shared__ T lds[2 * 4 * Sh::FS];
-
-    // workgroup -> tile: consecutive tiles (x fastest, then y, then z chunk)
-    // go to the same XCD, which receives every 8th workgroup
-    int b = blockIdx.x;
-    const int nb = gridDim.x;
-    if (remap && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int tix = b % ntx;
-    const int tiy = (b / ntx) % nty;
-    const int ch = b / (ntx * nty);
-    const int x0 = tix * TX, y0 = tiy * TY;
-    const int zb = ch * zlen;
-    const int ze = min(zb + zlen, g.nz);
-    if (zb >= ze) return;
-
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     SweepCtx<T, TX, TY> X;
     X.plane_bytes = (unsigned)(g.plane * (long long)sizeof(T));
@@ -517,11 +514,76 @@ __global__ __launch_bounds__(TX* TY) void substep55_sweep(Geom g, Fields4<T> in,
     }
 }
 
+// WV > 0 asks the compiler to fit WV waves per SIMD (a register budget of
+// 512 / WV per lane); 0 leaves the choice to the compiler.
+template <int WV>
+struct WavesAttr {
+    static constexpr int lo = WV > 0 ? WV : 1;
+    static constexpr int hi = WV > 0 ? WV : 8;
+};
+
+template <typename T, typename TW, int TX, int TY, int S, int WV>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WavesAttr<WV>::lo,
+                                                                         WavesAttr<WV>::hi)))
+void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out,
+                                                          Fields4<TW> w, Coef<T> cf,
+                                                          RKCoef<TW> rk, int ntx, int nty,
+                                                          int zlen, int remap) {
+    using Sh = SweepShape<T, TX, TY>;
+    __shared__ T lds[2 * 4 * Sh::FS];
+
+    // workgroup -> tile: consecutive tiles (x fastest, then y, then z chunk)
+    // go to the same XCD, which receives every 8th workgroup
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if (remap && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int tix = b % ntx;
+    const int tiy = (b / ntx) % nty;
+    const int ch = b / (ntx * nty);
+    const int zb = ch * zlen;
+    const int ze = min(zb + zlen, g.nz);
+    if (zb >= ze) return;
+    sweep_tile<T, TW, TX, TY, S>(g, in, out, w, cf, rk, tix * TX, tiy * TY, zb, ze, lds);
+}
+
+// Batched form: one persistent launch advances every box of an ensemble by
+// one substep.  The host lists the tile-chunks of all boxes (longest first);
+// workgroup b takes list entries remap(b), remap(b) + G, ... where the remap
+// gives each XCD a contiguous run of the list, so that tiles of one box share
+// that XCD's L2.  Per-box geometry, pointers, coefficients and time step come
+// from device memory, so a captured graph never needs re-capture when they
+// change.  Per point the arithmetic is the single-box kernel's.
+template <typename T, typename TW, int TX, int TY, int S, int WV>
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WavesAttr<WV>::lo,
+                                                                         WavesAttr<WV>::hi)))
+void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
+                                                          const BatchItem* __restrict__ items,
+                                                          int nitems, int parity, TW alpha,
+                                                          TW beta) {
+    using Sh = SweepShape<T, TX, TY>;
+    __shared__ T lds[2 * 4 * Sh::FS];
+    const int G = gridDim.x;
+    int b = blockIdx.x;
+    if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
+    for (int it = b; it < nitems; it += G) {
+        const BatchItem wi = items[it];
+        const BatchBox<T, TW>* bx = boxes + wi.box;
+        const Geom g = bx->g;
+        const Coef<T> cf = bx->cf;
+        const Fields4<T> in = bx->st[parity], out = bx->st[parity ^ 1];
+        const Fields4<TW> w = bx->w;
+        const RKCoef<TW> rk{alpha, beta, bx->dt};
+        sweep_tile<T, TW, TX, TY, S>(g, in, out, w, cf, rk, wi.x0, wi.y0, wi.zb, wi.ze, lds);
+        __syncthreads();  // the next item's first LDS write must follow every read
+    }
+}
+
 // Tile configurations (TX, TY).  Index 0 is the direct kernel.
 struct TileCfg {
-    int tx, ty;
+    int tx, ty, waves;
 };
-constexpr TileCfg kTiles[] = {{0, 0}, {64, 4}, {64, 2}, {32, 8}, {64, 8}, {128, 4}, {128, 2}};
+constexpr TileCfg kTiles[] = {{0, 0, 0},   {64, 4, 0},  {64, 2, 0}, {32, 8, 0}, {64, 8, 0},
+                              {128, 4, 0}, {128, 2, 0}, {64, 6, 0}, {64, 4, 3}, {64, 6, 3}};
 
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
@@ -534,7 +596,7 @@ int xcd_remap() {
     return v;
 }
 
-template <typename T, typename TW, int TX, int TY>
+template <typename T, typename TW, int TX, int TY, int WV = 0>
 hipError_t launch_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                         const Coef<T>& c, const RKCoef<TW>& rk, int s, hipStream_t st) {
     const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
@@ -553,15 +615,15 @@ hipError_t launch_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW
     const int rm = xcd_remap();
     switch (s) {
     case 1:
-        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 1>), grid, block, 0, st, g, in, out,
+        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 1, WV>), grid, block, 0, st, g, in, out,
                            w, c, rk, ntx, nty, zlen, rm);
         break;
     case 2:
-        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 2>), grid, block, 0, st, g, in, out,
+        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 2, WV>), grid, block, 0, st, g, in, out,
                            w, c, rk, ntx, nty, zlen, rm);
         break;
     default:
-        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 3>), grid, block, 0, st, g, in, out,
+        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 3, WV>), grid, block, 0, st, g, in, out,
                            w, c, rk, ntx, nty, zlen, rm);
         break;
     }
@@ -605,11 +667,95 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
     case 4: return launch_sweep<T, TW, 64, 8>(g, in, out, w, c, rk, s, st);
     case 5: return launch_sweep<T, TW, 128, 4>(g, in, out, w, c, rk, s, st);
     case 6: return launch_sweep<T, TW, 128, 2>(g, in, out, w, c, rk, s, st);
+    case 7: return launch_sweep<T, TW, 64, 6>(g, in, out, w, c, rk, s, st);
+    case 8: return launch_sweep<T, TW, 64, 4, 3>(g, in, out, w, c, rk, s, st);
+    case 9: return launch_sweep<T, TW, 64, 6, 3>(g, in, out, w, c, rk, s, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 bool substep55_reads_ghosts(int tile) { return tile == 0; }
+
+namespace {
+template <typename T, typename TW, int TX, int TY, int WV = 0>
+hipError_t launch_batch_t(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                          int grid, int parity, int s, TW alpha, TW beta, hipStream_t st) {
+    const dim3 block(TX * TY);
+    switch (s) {
+    case 1:
+        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 1, WV>), dim3(grid), block, 0, st, boxes,
+                           items, nitems, parity, alpha, beta);
+        break;
+    case 2:
+        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 2, WV>), dim3(grid), block, 0, st, boxes,
+                           items, nitems, parity, alpha, beta);
+        break;
+    default:
+        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 3, WV>), dim3(grid), block, 0, st, boxes,
+                           items, nitems, parity, alpha, beta);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, typename TW, int TX, int TY, int WV = 0>
+int batch_occupancy_t() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, substep55_batch<T, TW, TX, TY, 2, WV>,
+                                                     TX * TY, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+}  // namespace
+
+int substep55_tile_dims(int tile, int* tx, int* ty) {
+    if (tile <= 0 || tile >= kNumTiles) return -1;
+    *tx = kTiles[tile].tx;
+    *ty = kTiles[tile].ty;
+    return 0;
+}
+
+template <typename T, typename TW>
+hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                          int grid, int parity, int s, int tile, TW alpha, TW beta,
+                          hipStream_t st) {
+    switch (tile) {
+    case 1: return launch_batch_t<T, TW, 64, 4>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 2: return launch_batch_t<T, TW, 64, 2>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 3: return launch_batch_t<T, TW, 32, 8>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 4: return launch_batch_t<T, TW, 64, 8>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 5: return launch_batch_t<T, TW, 128, 4>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 6: return launch_batch_t<T, TW, 128, 2>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 7: return launch_batch_t<T, TW, 64, 6>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 8: return launch_batch_t<T, TW, 64, 4, 3>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 9: return launch_batch_t<T, TW, 64, 6, 3>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, typename TW>
+int batch55_blocks_per_cu(int tile) {
+    switch (tile) {
+    case 1: return batch_occupancy_t<T, TW, 64, 4>();
+    case 2: return batch_occupancy_t<T, TW, 64, 2>();
+    case 3: return batch_occupancy_t<T, TW, 32, 8>();
+    case 4: return batch_occupancy_t<T, TW, 64, 8>();
+    case 5: return batch_occupancy_t<T, TW, 128, 4>();
+    case 6: return batch_occupancy_t<T, TW, 128, 2>();
+    case 7: return batch_occupancy_t<T, TW, 64, 6>();
+    case 8: return batch_occupancy_t<T, TW, 64, 4, 3>();
+    case 9: return batch_occupancy_t<T, TW, 64, 6, 3>();
+    default: return 1;
+    }
+}
+
+#define FD6_INST_BATCH(T, TW)                                                                  \
+    template hipError_t launch_batch55<T, TW>(const BatchBox<T, TW>*, const BatchItem*, int,   \
+                                              int, int, int, int, TW, TW, hipStream_t);        \
+    template int batch55_blocks_per_cu<T, TW>(int);
+FD6_INST_BATCH(double, double)
+FD6_INST_BATCH(float, float)
+FD6_INST_BATCH(float, double)
 
 template hipError_t launch_substep55<double, double>(const Geom&, Fields4<double>,
                                                      Fields4<double>, Fields4<double>,

@@ -114,3 +114,36 @@ def test_create_validation_and_state_machine(pkg):
         assert lib.fd6_destroy(h) == 0
     assert lib.fd6_destroy(None) == 0
     assert lib.fd6_last_error(None) == b""
+
+
+def test_batch_validation(pkg):
+    lib = pkg.library()
+    out = ctypes.c_size_t()
+    arr = (pkg.Fd6Desc * 3)(desc(8, 8, 8), desc(16, 12, 10), desc(32, 32, 32))
+    assert lib.fd6_batch_workspace_bytes(3, arr, ctypes.byref(out)) == 0
+    single = ctypes.c_size_t()
+    lib.fd6_workspace_bytes(ctypes.byref(desc(32, 32, 32)), ctypes.byref(single))
+    assert out.value > 0
+    assert lib.fd6_batch_workspace_bytes(0, arr, ctypes.byref(out)) == -1
+    mixed = (pkg.Fd6Desc * 2)(desc(8, 8, 8, prec=0), desc(8, 8, 8, prec=1))
+    assert lib.fd6_batch_workspace_bytes(2, mixed, ctypes.byref(out)) == -1
+    v19 = (pkg.Fd6Desc * 1)(desc(8, 8, 8, var=1))
+    assert lib.fd6_batch_workspace_bytes(1, v19, ctypes.byref(out)) == -6
+    bad = (pkg.Fd6Desc * 1)(desc(5, 8, 8))
+    assert lib.fd6_batch_workspace_bytes(1, bad, ctypes.byref(out)) == -1
+    # state machine without a device: create only carves the pointer
+    lib.fd6_batch_workspace_bytes(3, arr, ctypes.byref(out))
+    h = ctypes.c_void_p()
+    assert lib.fd6_batch_create(3, arr, ctypes.c_void_p(1 << 40), out.value - 1, None,
+                                ctypes.byref(h)) == -3
+    assert lib.fd6_batch_create(3, arr, ctypes.c_void_p(1 << 40), out.value, None,
+                                ctypes.byref(h)) == 0
+    try:
+        assert lib.fd6_batch_step(h, 1) == -2
+        assert lib.fd6_batch_set_schedule(h, 0, 0) == -1
+        assert lib.fd6_batch_set_schedule(h, 1, -1) == -1
+        buf = (ctypes.c_double * 8)()
+        assert lib.fd6_batch_init_fields(h, 3, buf, buf, buf, buf) == -1
+        assert lib.fd6_batch_get_fields(h, 0, buf, buf, buf, buf) == -2
+    finally:
+        assert lib.fd6_batch_destroy(h) == 0
