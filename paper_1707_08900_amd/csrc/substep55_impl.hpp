@@ -25,6 +25,8 @@
 //  * The z loop is unrolled by 8 so every ring index is a compile-time
 //    register; the workgroup-to-tile map keeps neighbouring tiles on one XCD
 //    so y-halo rows are served from that XCD's L2.
+#pragma once
+
 #include <cstdlib>
 
 #include "fd6_internal.hpp"
@@ -173,15 +175,24 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
 
-template <typename T, int TX, int TY>
+// LD = false: the next plane is loaded into registers and written to LDS by
+// the threads; LD = true: it is copied by the buffer unit straight into LDS
+// (64 consecutive dwords per wave instruction), with no staging registers.
+template <typename T, int TX, int TY, bool LD = false>
 struct SweepShape {
     static constexpr int NT = TX * TY;
+    static constexpr int NW = NT / 64;              // wavefronts per workgroup
     static constexpr int W = TX + 2 * kR;           // LDS row length
     static constexpr int H = TY + 2 * kR;           // LDS rows
     static constexpr int PLANE = W * H;             // LDS elements per field plane
-    static constexpr int FS = PLANE + 1;            // field stride; cell PLANE is a dummy
     static constexpr int HALO = 2 * kR * W + 2 * kR * TY;  // halo cells per plane
-    static constexpr int NH = (HALO + NT - 1) / NT; // halo loads per thread
+    static constexpr int NH = (HALO + NT - 1) / NT; // halo loads per thread (LD = false)
+    static constexpr int DPE = (int)sizeof(T) / 4;  // dwords per element
+    static constexpr int NCH = (PLANE * DPE + 63) / 64;  // 64-dword chunks per plane (LD)
+    static constexpr int ND = (NCH + NW - 1) / NW;  // chunk copies per wave and field (LD)
+    // field stride in LDS elements: LD pads to whole chunks; otherwise cell
+    // PLANE is a dummy target for unused halo slots
+    static constexpr int FS = LD ? NCH * 64 / DPE : PLANE + 1;
 };
 
 template <typename T, int NH>
@@ -193,9 +204,10 @@ struct SweepRegs {
     T ph[NH][4];  // prefetched halo values of the next plane
 };
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool LD = false>
 struct SweepCtx {
-    using Sh = SweepShape<T, TX, TY>;
+    using Sh = SweepShape<T, TX, TY, LD>;
+    unsigned doff[Sh::ND];  // LD: byte offset (from the plane's ghost corner) of each lane's dword
     // Byte offsets, relative to the ghost corner (-3, -3) of a plane, of the
     // cells this thread loads (beyond the plane: the load returns 0; those
     // cells are only read by threads whose outputs are dropped).
@@ -226,13 +238,41 @@ __device__ __forceinline__ void sweep_prefetch(SweepRegs<T, NH>& R, const SweepC
     }
 }
 
-template <int PH, int S, typename T, typename TW, int TX, int TY, int NH>
+// LDS pointer in the local address space (required by the LDS copy).
+template <typename T>
+using lds_t = __attribute__((address_space(3))) T*;
+
+// LD: copy plane `corner` of the four fields into one LDS buffer.  Chunk j
+// (64 dwords) is issued by wave j % NW; its lanes fetch the dwords whose byte
+// offsets were precomputed in doff (periodic images included).
+template <typename T, int TX, int TY>
+__device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
+                                          const Fields4<T>& in, long long corner, lds_t<T> buf) {
+    using Sh = SweepShape<T, TX, TY, true>;
+    const int wv = threadIdx.x / 64;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, X.plane_bytes);
+#pragma unroll
+        for (int js = 0; js < Sh::ND; ++js) {
+            const int j = wv + js * Sh::NW;
+            if (j < Sh::NCH) {
+                lds_t<T> dst = buf + f * Sh::FS + j * (64 / Sh::DPE);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void*)dst, 4, X.doff[js], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int PH, int S, bool LD, typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, NH>& R,
-                                           const SweepCtx<T, TX, TY>& X, T* lds,
+                                           const SweepCtx<T, TX, TY, LD>& X, T* lds,
+                                           lds_t<T> lds3,
                                            const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w,
                                            const Coef<T>& cf, const RKCoef<TW>& rk) {
-    using Sh = SweepShape<T, TX, TY>;
+    using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int W = Sh::W;
     const int t = t0 + PH;
     if (t >= nplanes) return;
@@ -240,30 +280,48 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     const int o = p - kR;       // output plane finished in this step
     const bool outstep = t >= 2 * kR;
 
-    // RK3 register of the output point, issued early
-    TW wv[4] = {TW(0), TW(0), TW(0), TW(0)};
-    if constexpr (S != 1) {
-        if (outstep) {
-#pragma unroll
-            for (int f = 0; f < 4; ++f)
-                wv[f] = bload((TW*)nullptr, plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes),
-                              X.lane_w);
-        }
-    }
-
-    // prefetched plane p -> LDS buffer (PH & 1)
     T* buf = lds + (PH & 1) * 4 * Sh::FS;
     const int ci = (threadIdx.x / TX + kR) * W + (threadIdx.x % TX + kR);
+    TW wv[4] = {TW(0), TW(0), TW(0), TW(0)};
+    if constexpr (!LD) {
+        // RK3 register of the output point, issued early
+        if constexpr (S != 1) {
+            if (outstep) {
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        buf[f * Sh::FS + ci] = R.pf[f];
+                for (int f = 0; f < 4; ++f)
+                    wv[f] = bload((TW*)nullptr,
+                                  plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes),
+                                  X.lane_w);
+            }
+        }
+        // prefetched plane p -> LDS buffer (PH & 1)
 #pragma unroll
-        for (int h = 0; h < NH; ++h) buf[f * Sh::FS + X.loff_h[h]] = R.ph[h][f];
+        for (int f = 0; f < 4; ++f) {
+            buf[f * Sh::FS + ci] = R.pf[f];
+#pragma unroll
+            for (int h = 0; h < NH; ++h) buf[f * Sh::FS + X.loff_h[h]] = R.ph[h][f];
+        }
+        // next plane -> registers
+        if (t + 1 < nplanes)
+            sweep_prefetch<T, TX, TY, NH>(R, X, in, plane_corner(g, p + 1));
+        __syncthreads();
+    } else {
+        // this wave's copies of plane p are complete before the barrier; after
+        // it the other buffer (read in the previous step by every wave) takes
+        // plane p + 1
+        __syncthreads();
+        if (t + 1 < nplanes)
+            sweep_dma<T, TX, TY>(X, in, plane_corner(g, p + 1), lds3 + ((PH + 1) & 1) * 4 * Sh::FS);
+        if constexpr (S != 1) {
+            if (outstep) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    wv[f] = bload((TW*)nullptr,
+                                  plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes),
+                                  X.lane_w);
+            }
+        }
     }
-    // next plane -> registers
-    if (t + 1 < nplanes)
-        sweep_prefetch<T, TX, TY, NH>(R, X, in, plane_corner(g, p + 1));
-    __syncthreads();
 
     // ---- plane quantities of plane p for this thread's column ----
     // Stencils use their integer weights; grid spacing and viscosity enter
@@ -435,15 +493,15 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
 // One tile-chunk: columns [x0, x0 + TX) x [y0, y0 + TY) of the box, output
 // planes [zb, ze).  Every thread of the workgroup calls it with the same
 // arguments.
-template <typename T, typename TW, int TX, int TY, int S>
+template <typename T, typename TW, int TX, int TY, int S, bool LD>
 __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w,
                                            const Coef<T>& cf, const RKCoef<TW>& rk, int x0,
-                                           int y0, int zb, int ze, T* lds) {
-    using Sh = SweepShape<T, TX, TY>;
+                                           int y0, int zb, int ze, T* lds, lds_t<T> lds3) {
+    using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int NH = Sh::NH;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    SweepCtx<T, TX, TY> X;
+    SweepCtx<T, TX, TY, LD> X;
     X.plane_bytes = (unsigned)(g.plane * (long long)sizeof(T));
     X.wplane_bytes = (unsigned)(g.wplane * (long long)sizeof(TW));
     // Periodic boundary condition (Sec. 4) resolved in the loader: a halo cell
@@ -457,6 +515,18 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         const int iy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
         return (unsigned)(((iy + kR) * g.px + (ix + kR)) * (int)sizeof(T));
     };
+    if constexpr (LD) {
+        // dword d = 64 j + lane of the padded plane tile, j = wave + js NW
+        const int lane = threadIdx.x & 63, wv = threadIdx.x / 64;
+#pragma unroll
+        for (int js = 0; js < Sh::ND; ++js) {
+            const int d = 64 * (wv + js * Sh::NW) + lane;
+            const int e = d / Sh::DPE, half = d % Sh::DPE;
+            const int r = e / Sh::W, c = e - (e / Sh::W) * Sh::W;
+            const unsigned o = e < Sh::PLANE ? wrapped_off(x0 - kR + c, y0 - kR + r) : kDropOffset;
+            X.doff[js] = o == kDropOffset ? kDropOffset : o + 4u * (unsigned)half;
+        }
+    }
     X.goff_int = wrapped_off(x0 + tx, y0 + ty);
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
@@ -501,16 +571,19 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         for (int s = 0; s < 8; ++s) R.L[i][s] = T(0);
 
     const int nplanes = (ze - zb) + 2 * kR;
-    sweep_prefetch<T, TX, TY, NH>(R, X, in, plane_corner(g, zb - kR));
+    if constexpr (LD)
+        sweep_dma<T, TX, TY>(X, in, plane_corner(g, zb - kR), lds3);
+    else
+        sweep_prefetch<T, TX, TY, NH>(R, X, in, plane_corner(g, zb - kR));
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        sweep_step<0, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
-        sweep_step<1, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
-        sweep_step<2, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
-        sweep_step<3, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
-        sweep_step<4, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
-        sweep_step<5, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
-        sweep_step<6, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
-        sweep_step<7, S>(t0, nplanes, zb, R, X, lds, g, in, out, w, cf, rk);
+        sweep_step<0, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
+        sweep_step<1, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
+        sweep_step<2, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
+        sweep_step<3, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
+        sweep_step<4, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
+        sweep_step<5, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
+        sweep_step<6, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
+        sweep_step<7, S, LD>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, cf, rk);
     }
 }
 
@@ -522,14 +595,14 @@ struct WavesAttr {
     static constexpr int hi = WV > 0 ? WV : 8;
 };
 
-template <typename T, typename TW, int TX, int TY, int S, int WV>
+template <typename T, typename TW, int TX, int TY, int S, int WV, bool LD>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WavesAttr<WV>::lo,
                                                                          WavesAttr<WV>::hi)))
 void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out,
                                                           Fields4<TW> w, Coef<T> cf,
                                                           RKCoef<TW> rk, int ntx, int nty,
                                                           int zlen, int remap) {
-    using Sh = SweepShape<T, TX, TY>;
+    using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
 
     // workgroup -> tile: consecutive tiles (x fastest, then y, then z chunk)
@@ -543,7 +616,8 @@ void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out,
     const int zb = ch * zlen;
     const int ze = min(zb + zlen, g.nz);
     if (zb >= ze) return;
-    sweep_tile<T, TW, TX, TY, S>(g, in, out, w, cf, rk, tix * TX, tiy * TY, zb, ze, lds);
+    sweep_tile<T, TW, TX, TY, S, LD>(g, in, out, w, cf, rk, tix * TX, tiy * TY, zb, ze, lds,
+                                     (lds_t<T>)lds);
 }
 
 // Batched form: one persistent launch advances every box of an ensemble by
@@ -553,14 +627,14 @@ void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out,
 // that XCD's L2.  Per-box geometry, pointers, coefficients and time step come
 // from device memory, so a captured graph never needs re-capture when they
 // change.  Per point the arithmetic is the single-box kernel's.
-template <typename T, typename TW, int TX, int TY, int S, int WV>
+template <typename T, typename TW, int TX, int TY, int S, int WV, bool LD>
 __global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(WavesAttr<WV>::lo,
                                                                          WavesAttr<WV>::hi)))
 void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
                                                           const BatchItem* __restrict__ items,
                                                           int nitems, int parity, TW alpha,
                                                           TW beta) {
-    using Sh = SweepShape<T, TX, TY>;
+    using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
     const int G = gridDim.x;
     int b = blockIdx.x;
@@ -573,22 +647,28 @@ void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
         const Fields4<T> in = bx->st[parity], out = bx->st[parity ^ 1];
         const Fields4<TW> w = bx->w;
         const RKCoef<TW> rk{alpha, beta, bx->dt};
-        sweep_tile<T, TW, TX, TY, S>(g, in, out, w, cf, rk, wi.x0, wi.y0, wi.zb, wi.ze, lds);
+        sweep_tile<T, TW, TX, TY, S, LD>(g, in, out, w, cf, rk, wi.x0, wi.y0, wi.zb, wi.ze, lds,
+                                         (lds_t<T>)lds);
         __syncthreads();  // the next item's first LDS write must follow every read
     }
 }
 
 // Tile configurations (TX, TY).  Index 0 is the direct kernel.
+// waves: register budget target (0 = compiler's choice); ld: LDS loader.
 struct TileCfg {
     int tx, ty, waves;
+    bool ld;
 };
-constexpr TileCfg kTiles[] = {{0, 0, 0},   {64, 4, 0},  {64, 2, 0}, {32, 8, 0}, {64, 8, 0},
-                              {128, 4, 0}, {128, 2, 0}, {64, 6, 0}, {64, 4, 3}, {64, 6, 3}};
+constexpr TileCfg kTiles[] = {
+    {0, 0, 0, false},    {64, 4, 0, false}, {64, 2, 0, false}, {32, 8, 0, false},
+    {64, 8, 0, false},   {128, 4, 0, false}, {128, 2, 0, false}, {64, 6, 0, false},
+    {64, 4, 3, false},   {64, 6, 3, false}, {64, 8, 0, true},   {128, 4, 0, true},
+    {64, 4, 3, true},    {64, 6, 3, true},  {32, 8, 0, true},   {64, 4, 0, true}};
 
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // Workgroup-to-XCD remapping of tiles (FD6_XCD_REMAP=0 disables it).
-int xcd_remap() {
+inline int xcd_remap() {
     static const int v = [] {
         const char* e = getenv("FD6_XCD_REMAP");
         return (e && e[0] == '0') ? 0 : 1;
@@ -596,7 +676,7 @@ int xcd_remap() {
     return v;
 }
 
-template <typename T, typename TW, int TX, int TY, int WV = 0>
+template <typename T, typename TW, int TX, int TY, int WV = 0, bool LD = false>
 hipError_t launch_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                         const Coef<T>& c, const RKCoef<TW>& rk, int s, hipStream_t st) {
     const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
@@ -615,15 +695,15 @@ hipError_t launch_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW
     const int rm = xcd_remap();
     switch (s) {
     case 1:
-        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 1, WV>), grid, block, 0, st, g, in, out,
+        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 1, WV, LD>), grid, block, 0, st, g, in, out,
                            w, c, rk, ntx, nty, zlen, rm);
         break;
     case 2:
-        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 2, WV>), grid, block, 0, st, g, in, out,
+        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 2, WV, LD>), grid, block, 0, st, g, in, out,
                            w, c, rk, ntx, nty, zlen, rm);
         break;
     default:
-        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 3, WV>), grid, block, 0, st, g, in, out,
+        hipLaunchKernelGGL((substep55_sweep<T, TW, TX, TY, 3, WV, LD>), grid, block, 0, st, g, in, out,
                            w, c, rk, ntx, nty, zlen, rm);
         break;
     }
@@ -653,7 +733,6 @@ hipError_t launch_direct(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<T
 
 }  // namespace
 
-int substep55_tile_count() { return kNumTiles; }
 
 template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
@@ -670,50 +749,49 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
     case 7: return launch_sweep<T, TW, 64, 6>(g, in, out, w, c, rk, s, st);
     case 8: return launch_sweep<T, TW, 64, 4, 3>(g, in, out, w, c, rk, s, st);
     case 9: return launch_sweep<T, TW, 64, 6, 3>(g, in, out, w, c, rk, s, st);
+    case 10: return launch_sweep<T, TW, 64, 8, 0, true>(g, in, out, w, c, rk, s, st);
+    case 11: return launch_sweep<T, TW, 128, 4, 0, true>(g, in, out, w, c, rk, s, st);
+    case 12: return launch_sweep<T, TW, 64, 4, 3, true>(g, in, out, w, c, rk, s, st);
+    case 13: return launch_sweep<T, TW, 64, 6, 3, true>(g, in, out, w, c, rk, s, st);
+    case 14: return launch_sweep<T, TW, 32, 8, 0, true>(g, in, out, w, c, rk, s, st);
+    case 15: return launch_sweep<T, TW, 64, 4, 0, true>(g, in, out, w, c, rk, s, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-bool substep55_reads_ghosts(int tile) { return tile == 0; }
 
 namespace {
-template <typename T, typename TW, int TX, int TY, int WV = 0>
+template <typename T, typename TW, int TX, int TY, int WV = 0, bool LD = false>
 hipError_t launch_batch_t(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
                           int grid, int parity, int s, TW alpha, TW beta, hipStream_t st) {
     const dim3 block(TX * TY);
     switch (s) {
     case 1:
-        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 1, WV>), dim3(grid), block, 0, st, boxes,
+        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 1, WV, LD>), dim3(grid), block, 0, st, boxes,
                            items, nitems, parity, alpha, beta);
         break;
     case 2:
-        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 2, WV>), dim3(grid), block, 0, st, boxes,
+        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 2, WV, LD>), dim3(grid), block, 0, st, boxes,
                            items, nitems, parity, alpha, beta);
         break;
     default:
-        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 3, WV>), dim3(grid), block, 0, st, boxes,
+        hipLaunchKernelGGL((substep55_batch<T, TW, TX, TY, 3, WV, LD>), dim3(grid), block, 0, st, boxes,
                            items, nitems, parity, alpha, beta);
         break;
     }
     return hipGetLastError();
 }
 
-template <typename T, typename TW, int TX, int TY, int WV = 0>
+template <typename T, typename TW, int TX, int TY, int WV = 0, bool LD = false>
 int batch_occupancy_t() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, substep55_batch<T, TW, TX, TY, 2, WV>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, substep55_batch<T, TW, TX, TY, 2, WV, LD>,
                                                      TX * TY, 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 }  // namespace
 
-int substep55_tile_dims(int tile, int* tx, int* ty) {
-    if (tile <= 0 || tile >= kNumTiles) return -1;
-    *tx = kTiles[tile].tx;
-    *ty = kTiles[tile].ty;
-    return 0;
-}
 
 template <typename T, typename TW>
 hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
@@ -729,6 +807,12 @@ hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, 
     case 7: return launch_batch_t<T, TW, 64, 6>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
     case 8: return launch_batch_t<T, TW, 64, 4, 3>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
     case 9: return launch_batch_t<T, TW, 64, 6, 3>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 10: return launch_batch_t<T, TW, 64, 8, 0, true>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 11: return launch_batch_t<T, TW, 128, 4, 0, true>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 12: return launch_batch_t<T, TW, 64, 4, 3, true>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 13: return launch_batch_t<T, TW, 64, 6, 3, true>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 14: return launch_batch_t<T, TW, 32, 8, 0, true>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
+    case 15: return launch_batch_t<T, TW, 64, 4, 0, true>(boxes, items, nitems, grid, parity, s, alpha, beta, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -745,28 +829,14 @@ int batch55_blocks_per_cu(int tile) {
     case 7: return batch_occupancy_t<T, TW, 64, 6>();
     case 8: return batch_occupancy_t<T, TW, 64, 4, 3>();
     case 9: return batch_occupancy_t<T, TW, 64, 6, 3>();
+    case 10: return batch_occupancy_t<T, TW, 64, 8, 0, true>();
+    case 11: return batch_occupancy_t<T, TW, 128, 4, 0, true>();
+    case 12: return batch_occupancy_t<T, TW, 64, 4, 3, true>();
+    case 13: return batch_occupancy_t<T, TW, 64, 6, 3, true>();
+    case 14: return batch_occupancy_t<T, TW, 32, 8, 0, true>();
+    case 15: return batch_occupancy_t<T, TW, 64, 4, 0, true>();
     default: return 1;
     }
 }
-
-#define FD6_INST_BATCH(T, TW)                                                                  \
-    template hipError_t launch_batch55<T, TW>(const BatchBox<T, TW>*, const BatchItem*, int,   \
-                                              int, int, int, int, TW, TW, hipStream_t);        \
-    template int batch55_blocks_per_cu<T, TW>(int);
-FD6_INST_BATCH(double, double)
-FD6_INST_BATCH(float, float)
-FD6_INST_BATCH(float, double)
-
-template hipError_t launch_substep55<double, double>(const Geom&, Fields4<double>,
-                                                     Fields4<double>, Fields4<double>,
-                                                     const Coef<double>&, const RKCoef<double>&,
-                                                     int, int, hipStream_t);
-template hipError_t launch_substep55<float, float>(const Geom&, Fields4<float>, Fields4<float>,
-                                                   Fields4<float>, const Coef<float>&,
-                                                   const RKCoef<float>&, int, int, hipStream_t);
-template hipError_t launch_substep55<float, double>(const Geom&, Fields4<float>, Fields4<float>,
-                                                    Fields4<double>, const Coef<float>&,
-                                                    const RKCoef<double>&, int, int,
-                                                    hipStream_t);
 
 }  // namespace fd6

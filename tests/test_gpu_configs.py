@@ -1,0 +1,173 @@
+"""Parity at the benchmark configurations' own sizes.
+
+* 128^3, 16 random-phase modes |k| <= 8, A = 1e-2, nu = 2e-3, 100 RK3 steps:
+  the full fields against the FP64 oracle, both discretisations.
+* 512^3 (and 256^3) single box, FP32, |k| <= 16, A = 0.1, nu = 1e-3: one step
+  in the benchmark's kernel shape, sampled points against the oracle's local
+  patch update (a point after one step depends only on a 19^3 neighbourhood).
+* 768^3 linear sound wave lnrho = 1e-4 sin(4x), u = 0, nu = 1e-4: the
+  x-profile equals the oracle's exact 768 x 8 x 8 slab replica (the field
+  never varies in y and z), every column is identical, and the wave follows
+  the fully discrete 2x2 closed form.
+* the 64-box ensemble: every box bitwise equal to its single-box run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fd6():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible ROCm GPU")
+    import paper_1707_08900_amd as p
+    return p
+
+
+def rel_err(a, b):
+    return max(float(np.max(np.abs(x - y)) / max(np.max(np.abs(y)), 1e-300))
+               for x, y in zip(a, b))
+
+
+@pytest.fixture(scope="module")
+def mid():
+    return si.mid_box(128)
+
+
+@pytest.mark.parametrize("variant", ["55p", "19p"])
+def test_mid_box_100_steps(fd6, orc, mid, variant):
+    w = mid
+    ref = orc.rk3(w.fields, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, variant, 100, 16)
+    box = fd6.Box(w.shape, "fp64", variant)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(w.fields)
+    box.step(100)
+    out = box.get_fields()
+    e64 = rel_err(out, ref)
+    print(f"128^3 x 100 steps {variant} fp64: rel err {e64:.3e}", flush=True)
+    assert e64 <= 1e-11
+    b32 = fd6.Box(w.shape, "fp32", variant)
+    b32.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    b32.init_fields(w.fields)
+    b32.step(100)
+    ref32 = orc.rk3(si.as_float32_exact(w.fields), w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, variant,
+                    100, 16)
+    e32 = rel_err(b32.get_fields(), ref32)
+    print(f"128^3 x 100 steps {variant} fp32: rel err {e32:.3e}", flush=True)
+    assert e32 <= 1e-4
+
+
+def test_55p_and_19p_differ_only_slightly(fd6, mid):
+    """The two discretisations are distinct but their results practically
+    coincide (Sec. 6): after 100 steps they differ by far less than the
+    change the flow itself underwent."""
+    w = mid
+    outs = {}
+    for v in ("55p", "19p"):
+        box = fd6.Box(w.shape, "fp64", v)
+        box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+        box.init_fields(w.fields)
+        box.step(100)
+        outs[v] = box.get_fields()
+    for q in range(4):
+        diff = np.max(np.abs(outs["55p"][q] - outs["19p"][q]))
+        change = np.max(np.abs(outs["55p"][q] - w.fields[q]))
+        assert 0 < diff < 1e-2 * change, (q, diff, change)
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_large_box_sampled_points(fd6, orc, n):
+    import torch
+    w = si.large_box(n)
+    box = fd6.Box(w.shape, "fp32")
+    from paper_1707_08900_amd import tune
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    dev = [torch.from_numpy(f).cuda() for f in w.fields]
+    box.init_fields(dev)
+    tune.tune(box, steps=1, use_cache=False)
+    box.init_fields(dev)
+    box.step(1)
+    out = box.get_fields_device()
+    inp = si.as_float32_exact(w.fields)
+    scale = [float(np.max(np.abs(f))) for f in inp]
+    rng = np.random.default_rng(7)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, 0, n - 1)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(9)]
+    worst = 0.0
+    for c in pts:
+        ref = orc.rk3_point(inp, c, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1)
+        for q in range(4):
+            worst = max(worst, abs(float(out[q][c].item()) - ref[q]) / scale[q])
+    print(f"{n}^3 fp32 sampled rel err {worst:.3e}", flush=True)
+    assert worst <= 1e-5
+
+
+def sound_closed_form(k, h, cs, nu, dt, nsteps, A):
+    t = k * h
+    k1 = (45 * math.sin(t) - 9 * math.sin(2 * t) + math.sin(3 * t)) / (30 * h)
+    k2 = (490 - 540 * math.cos(t) + 54 * math.cos(2 * t) - 4 * math.cos(3 * t)) / (180 * h * h)
+    M = np.array([[0.0, k1], [-cs * cs * k1, -(4.0 / 3.0) * nu * k2]]) * dt
+    P = np.eye(2) + M + M @ M / 2 + M @ M @ M / 6
+    return np.linalg.matrix_power(P, nsteps) @ np.array([A, 0.0])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-3)])
+def test_sound_wave_768(fd6, orc, precision, tol):
+    import torch
+    n, nsteps = 768, 200
+    slab = si.sound_wave_box(shape=(8, 8, n))          # exact replica of the x-profile
+    full_dt = slab.dt
+    h = 2 * math.pi / n
+    ref = orc.rk3(slab.fields if precision == "fp64" else si.as_float32_exact(slab.fields),
+                  slab.nu, slab.cs, h, h, h, full_dt, "55p", nsteps, 16)
+    box = fd6.Box((n, n, n), precision)
+    box.set_params(slab.nu, slab.cs, h, h, h, full_dt)
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * h
+    lnrho = (1e-4 * torch.sin(4 * x)).expand(n, n, n).contiguous()
+    zero = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    box.init_fields([lnrho, zero, zero, zero])
+    del lnrho
+    box.step(nsteps)
+    out = box.get_fields_device()
+    lr = out[0]
+    ux = out[1]
+    # every (y, z) column carries the same x-profile, and uy = uz = 0
+    assert float((lr - lr[0:1, 0:1, :]).abs().max()) == 0.0
+    assert float(out[2].abs().max()) == 0.0 and float(out[3].abs().max()) == 0.0
+    prof = [lr[0, 0].cpu().numpy(), ux[0, 0].cpu().numpy()]
+    e = max(float(np.max(np.abs(prof[0] - ref[0][0, 0]))) / 1e-4,
+            float(np.max(np.abs(prof[1] - ref[1][0, 0]))) / 1e-4)
+    print(f"768^3 sound wave {precision}: profile err vs oracle slab {e:.3e}", flush=True)
+    assert e <= tol
+    # projection onto sin(4x) / cos(4x) against the fully discrete closed form
+    L = 2 / n * float(np.sum(prof[0] * np.sin(4 * x.cpu().numpy())))
+    U = 2 / n * float(np.sum(prof[1] * np.cos(4 * x.cpu().numpy())))
+    Lc, Uc = sound_closed_form(4, h, slab.cs, slab.nu, full_dt, nsteps, 1e-4)
+    assert abs(L - Lc) <= 1e-3 * 1e-4 and abs(U - Uc) <= 1e-3 * 1e-4
+
+
+def test_ensemble_64_boxes_bitwise(fd6):
+    members = si.ensemble(64)
+    ws = [m.workload for m in members]
+    b = fd6.Batch([w.shape for w in ws], "fp32")
+    b.set_params([(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt) for w in ws])
+    for i, w in enumerate(ws):
+        b.init_fields(i, w.fields)
+    tile = 3
+    b.set_schedule(tile, 32)
+    b.step(2)
+    for i in (0, 1, 7, 31, 63):
+        w = ws[i]
+        box = fd6.Box(w.shape, "fp32")
+        box.set_tile(tile)
+        box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+        box.init_fields(w.fields)
+        box.step(2)
+        for a, c in zip(b.get_fields(i), box.get_fields()):
+            assert np.array_equal(a, c), (i, w.shape)
