@@ -34,16 +34,20 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {("55p", "fp32"): 160, ("55p", "fp64"): 320, ("55p", "fp32_acc64"): 224,
              ("19p", "fp32"): 304, ("19p", "fp64"): 608}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_substep55_fp32_512.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1707_08900_amd", "csrc", "substep55.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1707_08900_amd", "csrc", f)
+               for f in ("sweep_common.hpp", "substep55_impl.hpp", "substep55_f32.hip")]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_sha(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_sha(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():
@@ -54,7 +58,7 @@ def load_traffic():
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha") != source_sha(KERNEL_SRC):
+    if t.get("kernel_source_sha") != source_sha(KERNEL_SRCS):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -63,7 +67,7 @@ def make_box(fd6, w, dev_fields, precision, variant, tune=True):
     box = fd6.Box(w.shape, precision, variant)
     box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
     tuned = None
-    if tune and variant == "55p":
+    if tune:
         from paper_1707_08900_amd import tune as tuner
         box.init_fields(dev_fields)
         tuned = tuner.tune(box, steps=2, use_cache=False)
@@ -118,6 +122,7 @@ def batch_form(torch, fd6, si, steps):
     """64 independent boxes (edges from {32, 48, 64, 96}, per-box nu and
     amplitude, FP32), one persistent launch per substep, graph per step.
     The kernel shape and z-chunk are tuned on the ensemble itself."""
+    import numpy as np
     members = si.ensemble(64)
     ws = [m.workload for m in members]
     pts = sum(int(np.prod(w.shape)) for w in ws)
@@ -132,7 +137,7 @@ def batch_form(torch, fd6, si, steps):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     timings = {}
-    for tile in (1, 3, 4):
+    for tile in (1, 4, 8):
         for zc in (0, 32):
             b.set_schedule(tile, zc)
             b.step(1)

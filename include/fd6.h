@@ -159,10 +159,13 @@ int fd6_reduce_device(fd6_box *box, double *d_out5);
  * because alpha(1) = 0.  Synchronises. */
 int fd6_rhs(fd6_box *box, double *r_lnrho, double *r_ux, double *r_uy, double *r_uz);
 
-/* Kernel shape of the 55-point substep: 0 = one thread per point with every
- * tap read through the caches; 1 .. fd6_tile_count()-1 = z-sweep kernels
- * with different xy tile shapes.  Results are identical up to rounding
- * order; the choice only changes speed (see the autotuner). */
+/* Kernel shape of the substep kernels (both methods): 0 = direct kernels, one
+ * thread per point with every tap read through the caches from the ghost
+ * zone, which a separate pass refreshes; 1 .. fd6_tile_count()-1 = z-sweep
+ * kernels (periodic images resolved by their loaders, no ghost pass) with
+ * different xy tile shapes and load pipelines.  Results agree up to rounding
+ * order (the z-sweep shapes bit for bit with each other); the choice only
+ * changes speed (see the autotuner).  Default: 2. */
 int fd6_tile_count(void);
 int fd6_set_tile(fd6_box *box, int32_t tile);
 

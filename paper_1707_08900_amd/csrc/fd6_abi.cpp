@@ -42,7 +42,7 @@ struct fd6_box {
     double* staging = nullptr;
     long long staging_elems = 0;
     int cur = 0;
-    int tile = 4;
+    int tile = 2;  // 64 x 8 z-sweep
     bool ghosts_ok[2] = {false, false};  // ghost zone of each state set is current
     std::string err;
     // optional per-launch event timing
@@ -60,7 +60,7 @@ struct fd6_box {
 struct fd6_batch {
     int n = 0;
     int precision = 0;
-    int tile = 3;
+    int tile = 4;  // 32 x 8 z-sweep
     int zchunk = 0;  // 0: whole box per work item
     bool use_graph = true;
     hipStream_t stream = nullptr;   // caller's stream (graph launches, transfers)
@@ -270,6 +270,7 @@ Coef<T> make_coef(const fd6_params& p) {
         c.kxy[i] = T(-490.0 * (sx + sy));
     }
     for (int q = 0; q < 3; ++q) c.mu[q] = T(p.nu / (3.0 * 720.0 * h[pa[q]] * h[pb[q]]));
+    c.kp = T(-490.0 * (sg[0] + sg[1]));
     return c;
 }
 
@@ -291,7 +292,7 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
     Fields4<T> out = fields_of<T>(b->state[b->cur ^ 1]);
     Fields4<TW> w = fields_of<TW>(b->w);
     const Coef<T> c = make_coef<T>(b->params);
-    const bool needs_ghosts = b->desc.variant == FD6_19P || substep55_reads_ghosts(b->tile);
+    const bool needs_ghosts = substep55_reads_ghosts(b->tile);
     int rc = FD6_OK;
     if (needs_ghosts && !b->ghosts_ok[b->cur]) {
         rc = timed(b, b->ev_ghost, [&]() -> int {
@@ -310,18 +311,20 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
     } else {
         T* dv = static_cast<T*>(b->div);
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->stream)));
+            HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->tile, b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;
-        Fields4<T> d1{{dv, dv, dv, dv}};
-        rc = timed(b, b->ev_ghost, [&]() -> int {
-            HIPCHK(b, launch_ghost_fill<T>(g, d1, 1, b->stream));
-            return FD6_OK;
-        });
-        if (rc) return rc;
+        if (needs_ghosts) {  // the direct pass 2 reads the divergence's ghost zone
+            Fields4<T> d1{{dv, dv, dv, dv}};
+            rc = timed(b, b->ev_ghost, [&]() -> int {
+                HIPCHK(b, launch_ghost_fill<T>(g, d1, 1, b->stream));
+                return FD6_OK;
+            });
+            if (rc) return rc;
+        }
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, b->stream)));
+            HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, s, b->tile, b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;

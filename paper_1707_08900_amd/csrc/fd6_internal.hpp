@@ -74,7 +74,8 @@ struct Coef {
     //   sg[a]  = nu / (180 h_a^2),  sg4[a] = (4/3) sg[a]
     //   kxy[i] = -490 (s_ix + s_iy), s_ia = (a == i ? sg4 : sg)[a]
     //   mu[p]  = nu / (3 * 720 h_a h_b), p = xy, xz, yz
-    T sg[3], sg4[3], kxy[3], mu[3];
+    //   kp     = -490 (sg[x] + sg[y])  (centre weight of nu (D2x + D2y))
+    T sg[3], sg4[3], kxy[3], mu[3], kp;
 };
 
 // Host-side launchers (implemented in the .hip files).
@@ -123,13 +124,22 @@ hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, 
 template <typename T, typename TW>
 int batch55_blocks_per_cu(int tile);
 
-// 19-point method: pass 1 (divergence, partial update) and pass 2.
+// 19-point method: pass 1 (divergence, partial update) and pass 2 (the
+// (nu/3) grad div u term).  tile 0 runs the direct kernels, which read the
+// ghost zones of the state (pass 1) and of the divergence (pass 2); the
+// z-sweep shapes resolve periodic images themselves.
 template <typename T, typename TW>
 hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,
-                          const Coef<T>& c, const RKCoef<TW>& rk, int s, hipStream_t st);
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          hipStream_t st);
+template <typename T, typename TW>
+hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                                T* div, const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                                hipStream_t st);
 template <typename T, typename TW>
 hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
-                          const Coef<T>& c, const RKCoef<TW>& rk, hipStream_t st);
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          hipStream_t st);
 
 // FP64 reductions: per-block partials then one fixed-order final block.
 constexpr int kReduceBlocks = 1024;

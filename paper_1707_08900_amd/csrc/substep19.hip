@@ -1,14 +1,16 @@
 // 19-point two-pass substep (Sec. 4.2, Algorithm 3, Appendix A).
 //
-// Pass 1 computes the divergence field d = D1x ux + D1y uy + D1z uz (stored
-// with a ghost zone), the right-hand side without the (nu/3) grad(div u)
-// term, and the partial RK3 register and output.  After the periodic ghost
-// fill of d, pass 2 adds dt (nu/3) D1_i d to w_i and beta dt (nu/3) D1_i d to
-// the output velocity.  Both passes read only axis-aligned taps (19 points).
+// Pass 1 computes the divergence field d = D1x ux + D1y uy + D1z uz, the
+// right-hand side without the (nu/3) grad(div u) term, and the partial RK3
+// register and output.  Pass 2 adds dt (nu/3) D1_i d to w_i and
+// beta dt (nu/3) D1_i d to the output velocity.  Both passes read only
+// axis-aligned taps (19 points).
 //
-// gfx950 mapping: one thread per output point, 64-wide x rows per wavefront
-// (coalesced), 4 rows per workgroup; taps come through the L1/L2 caches.
-#include "fd6_internal.hpp"
+// This file holds the direct kernels of both passes (one thread per point,
+// taps through the caches from the ghost zones), the z-sweep form of pass 2,
+// and the dispatch of both passes; the z-sweep form of pass 1 shares the
+// 55-point sweep.
+#include "sweep_common.hpp"
 
 namespace fd6 {
 namespace {
@@ -105,11 +107,129 @@ __global__ __launch_bounds__(256) void pass19b_kernel(Geom g, const T* __restric
     }
 }
 
+// z-sweep form of pass 2: a TX x TY column tile sweeps a z chunk of d.
+// Each step puts one plane of d (tile + 3-cell halo, periodic images
+// resolved by the loader) into LDS, forms its x and y first derivatives for
+// the thread's column (kept 3 planes), and pushes the centre value into a
+// register queue of 7 planes for the z derivative; output plane p - 3 is
+// completed from them.  Substep 3 neither reads nor writes w.
+template <typename T, int NH>
+struct Pass2Regs {
+    T q[8];      // column of d over planes (ring)
+    T dx[4], dy[4];  // x / y first derivatives of d, ring of 4 planes
+    T pf;        // prefetched interior value of the next plane
+    T ph[NH];    // prefetched halo values of the next plane
+};
+
+template <typename T, int TX, int TY, int NH>
+__device__ __forceinline__ void pass2_prefetch(Pass2Regs<T, NH>& R,
+                                               const SweepCtx<T, TX, TY>& X, const T* dv,
+                                               long long corner) {
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(dv + corner, X.plane_bytes);
+    R.pf = bload((T*)nullptr, rs, X.goff_int);
+#pragma unroll
+    for (int h = 0; h < NH; ++h) R.ph[h] = bload((T*)nullptr, rs, X.goff_h[h]);
+}
+
+template <int PH, int S, typename T, typename TW, int TX, int TY, int NH>
+__device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Regs<T, NH>& R,
+                                           const SweepCtx<T, TX, TY>& X, T* lds, const Geom& g,
+                                           const T* dv, const Fields4<T>& out,
+                                           const Fields4<TW>& w, const Coef<T>& cf,
+                                           const RKCoef<TW>& rk, TW cgd) {
+    using Sh = SweepShape<T, TX, TY>;
+    constexpr int W = Sh::W;
+    const int t = t0 + PH;
+    if (t >= nplanes) return;
+    const int p = zb - kR + t;  // plane loaded in this step
+    const int o = p - kR;       // output plane finished in this step
+    const bool outstep = t >= 2 * kR;
+    const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
+    T ov[3] = {T(0), T(0), T(0)};
+    TW wv[3] = {TW(0), TW(0), TW(0)};
+    if (outstep) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            ov[i] = bload((T*)nullptr, plane_rsrc(out.f[1 + i] + ocorner, X.plane_bytes),
+                          X.lane_o);
+            if constexpr (S != 3)
+                wv[i] = bload((TW*)nullptr,
+                              plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, X.wplane_bytes),
+                              X.lane_w);
+        }
+    }
+    T* buf = lds + (PH & 1) * Sh::FS;
+    const int ci = (threadIdx.x / TX + kR) * W + (threadIdx.x % TX + kR);
+    buf[ci] = R.pf;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) buf[X.loff_h[h]] = R.ph[h];
+    if (t + 1 < nplanes) pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, p + 1));
+    __syncthreads();
+
+    const T* B = buf + ci;
+    R.q[sl8(PH)] = B[0];
+    R.dx[PH & 3] = cf.d1[0][0] * (B[1] - B[-1]) + cf.d1[0][1] * (B[2] - B[-2]) +
+                   cf.d1[0][2] * (B[3] - B[-3]);
+    R.dy[PH & 3] = cf.d1[1][0] * (B[W] - B[-W]) + cf.d1[1][1] * (B[2 * W] - B[-2 * W]) +
+                   cf.d1[1][2] * (B[3 * W] - B[-3 * W]);
+    if (outstep) {
+        const T dz = cf.d1[2][0] * (R.q[sl8(PH - 2)] - R.q[sl8(PH - 4)]) +
+                     cf.d1[2][1] * (R.q[sl8(PH - 1)] - R.q[sl8(PH - 5)]) +
+                     cf.d1[2][2] * (R.q[sl8(PH)] - R.q[sl8(PH - 6)]);
+        constexpr int DO = (PH + 1) & 3;  // slot of plane p - 3
+        const T gd[3] = {R.dx[DO], R.dy[DO], dz};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const TW tq = cgd * TW(gd[i]);
+            if constexpr (S != 3)
+                bstore(wv[i] + tq, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, X.wplane_bytes),
+                       X.lane_w);
+            bstore(T(TW(ov[i]) + rk.beta * tq),
+                   plane_rsrc(out.f[1 + i] + ocorner, X.plane_bytes), X.lane_o);
+        }
+    }
+}
+
+template <typename T, typename TW, int TX, int TY, int S>
+__global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __restrict__ dv,
+                                                          Fields4<T> out, Fields4<TW> w,
+                                                          Coef<T> cf, RKCoef<TW> rk, TW cgd,
+                                                          int ntx, int nty, int zlen,
+                                                          int remap) {
+    using Sh = SweepShape<T, TX, TY>;
+    constexpr int NH = Sh::NH;
+    __shared__ T lds[2 * Sh::FS];
+    const TileXY tl = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    if (tl.zb >= tl.ze) return;
+    SweepCtx<T, TX, TY> X;
+    sweep_ctx_init<T, TW, TX, TY, false>(X, g, tl.tx, tl.ty);
+    Pass2Regs<T, NH> R;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) R.q[s] = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) R.dx[s] = R.dy[s] = T(0);
+    const int zb = tl.zb;
+    const int nplanes = (tl.ze - zb) + 2 * kR;
+    pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, zb - kR));
+    for (int t0 = 0; t0 < nplanes; t0 += 8) {
+        pass2_step<0, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<1, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<2, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<3, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<4, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<5, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<6, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<7, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+    }
+}
+
 }  // namespace
 
 template <typename T, typename TW>
 hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,
-                          const Coef<T>& c, const RKCoef<TW>& rk, int s, hipStream_t st) {
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          hipStream_t st) {
+    if (tile != 0) return launch_pass19a_sweep<T, TW>(g, in, out, w, div, c, rk, s, tile, st);
     const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)g.nz);
     switch (s) {
     case 1:
@@ -124,21 +244,50 @@ hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<
     return hipGetLastError();
 }
 
+// Pass 2 takes the column tile of the chosen shape (its register budget and
+// loader options do not apply to this one-field sweep).
 template <typename T, typename TW>
 hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
-                          const Coef<T>& c, const RKCoef<TW>& rk, hipStream_t st) {
-    const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)g.nz);
-    hipLaunchKernelGGL((pass19b_kernel<T, TW>), grid, dim3(256), 0, st, g, div, out, w, c, rk,
-                       TW((double)rk.dt * c.nu3));
-    return hipGetLastError();
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          hipStream_t st) {
+    const TW cgd = TW((double)rk.dt * c.nu3);
+    return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
+        constexpr TileCfg k = kTiles[decltype(I)::value];
+        if constexpr (k.tx == 0) {
+            const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4),
+                            (unsigned)g.nz);
+            hipLaunchKernelGGL((pass19b_kernel<T, TW>), grid, dim3(256), 0, st, g, div, out, w, c,
+                               rk, cgd);
+        } else {
+            const SweepGrid sg = sweep_grid(g, k.tx, k.ty);
+            const dim3 grid(sg.blocks), block(k.tx * k.ty);
+            const int rm = xcd_remap();
+            switch (s) {
+            case 1:
+                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 1>), grid, block, 0, st, g,
+                                   div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                break;
+            case 2:
+                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 2>), grid, block, 0, st, g,
+                                   div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                break;
+            default:
+                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 3>), grid, block, 0, st, g,
+                                   div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                break;
+            }
+        }
+        return hipGetLastError();
+    });
 }
 
 #define FD6_INST19(T, TW)                                                                       \
     template hipError_t launch_pass19a<T, TW>(const Geom&, Fields4<T>, Fields4<T>, Fields4<TW>, \
-                                              T*, const Coef<T>&, const RKCoef<TW>&, int,      \
+                                              T*, const Coef<T>&, const RKCoef<TW>&, int, int, \
                                               hipStream_t);                                    \
     template hipError_t launch_pass19b<T, TW>(const Geom&, const T*, Fields4<T>, Fields4<TW>,   \
-                                              const Coef<T>&, const RKCoef<TW>&, hipStream_t);
+                                              const Coef<T>&, const RKCoef<TW>&, int, int,     \
+                                              hipStream_t);
 FD6_INST19(double, double)
 FD6_INST19(float, float)
 FD6_INST19(float, double)

@@ -1,7 +1,8 @@
-// Instantiations of the 55-point substep kernels for state type float and RK3
+// Instantiations of the z-sweep substep kernels (55-point single box and
+// batch, 19-point pass 1) for state type float and RK3
 // register type float (one translation unit per precision form keeps the
 // build parallel).
-#include "substep55_impl.hpp"
+#include "sweep_substep.hpp"
 
 namespace fd6 {
 
@@ -11,6 +12,9 @@ template hipError_t launch_substep55<float, float>(const Geom&, Fields4<float>, 
 template hipError_t launch_batch55<float, float>(const BatchBox<float, float>*, const BatchItem*, int,
                                             int, int, int, int, float, float, hipStream_t);
 template int batch55_blocks_per_cu<float, float>(int);
+template hipError_t launch_pass19a_sweep<float, float>(const Geom&, Fields4<float>, Fields4<float>,
+                                                  Fields4<float>, float*, const Coef<float>&,
+                                                  const RKCoef<float>&, int, int, hipStream_t);
 
 int substep55_tile_count() { return kNumTiles; }
 

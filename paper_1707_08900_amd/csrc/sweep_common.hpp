@@ -1,0 +1,216 @@
+// Building blocks shared by the z-sweep kernels of the 55-point and the
+// 19-point methods: raw buffer access, tile geometry, plane addressing.
+#pragma once
+
+#include <cstdlib>
+#include <type_traits>
+
+#include "fd6_internal.hpp"
+
+namespace fd6 {
+namespace {
+
+constexpr int sl8(int x) { return ((x % 8) + 8) % 8; }
+
+// Raw buffer access: an SGPR descriptor for one plane of one field plus a
+// 32-bit per-lane byte offset.  Loads beyond the descriptor's range return 0
+// and stores beyond it are dropped, which replaces bounds branches.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufFlags = 0x00020000;        // raw, untyped access (word 3)
+constexpr unsigned kDropOffset = 0x80000000u;  // beyond every plane's range
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, (int)bytes, kBufFlags);
+}
+__device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+
+// LD = false: the next plane is loaded into registers and written to LDS by
+// the threads; LD = true: it is copied by the buffer unit straight into LDS
+// (64 consecutive dwords per wave instruction), with no staging registers.
+template <typename T, int TX, int TY, bool LD = false>
+struct SweepShape {
+    static constexpr int NT = TX * TY;
+    static constexpr int NW = NT / 64;              // wavefronts per workgroup
+    static constexpr int W = TX + 2 * kR;           // LDS row length
+    static constexpr int H = TY + 2 * kR;           // LDS rows
+    static constexpr int PLANE = W * H;             // LDS elements per field plane
+    static constexpr int HALO = 2 * kR * W + 2 * kR * TY;  // halo cells per plane
+    static constexpr int NH = (HALO + NT - 1) / NT; // halo loads per thread (LD = false)
+    static constexpr int DPE = (int)sizeof(T) / 4;  // dwords per element
+    static constexpr int NCH = (PLANE * DPE + 63) / 64;  // 64-dword chunks per plane (LD)
+    static constexpr int ND = (NCH + NW - 1) / NW;  // chunk copies per wave and field (LD)
+    // field stride in LDS elements: LD pads to whole chunks; otherwise cell
+    // PLANE is a dummy target for unused halo slots
+    static constexpr int FS = LD ? NCH * 64 / DPE : PLANE + 1;
+};
+
+// Element index of the ghost corner (-3, -3) of interior plane p mod nz.
+__device__ __forceinline__ long long plane_corner(const Geom& g, int p) {
+    const int pz = p < 0 ? p + g.nz : (p >= g.nz ? p - g.nz : p);
+    return g.origin + (long long)pz * g.plane - kR * g.px - kR;
+}
+
+// LDS pointer in the local address space (required by the LDS copy).
+template <typename T>
+using lds_t = __attribute__((address_space(3))) T*;
+
+// Workgroup-to-XCD remapping of tiles (FD6_XCD_REMAP=0 disables it).
+inline int xcd_remap() {
+    static const int v = [] {
+        const char* e = getenv("FD6_XCD_REMAP");
+        return (e && e[0] == '0') ? 0 : 1;
+    }();
+    return v;
+}
+
+// Per-thread addressing of one tile: byte offsets, relative to the ghost
+// corner (-3, -3) of a plane, of the cells this thread loads (beyond the
+// plane's range the load returns 0; such cells are only read by threads whose
+// outputs are dropped), LDS slots of its halo loads, and its output offsets.
+template <typename T, int TX, int TY, bool LD = false>
+struct SweepCtx {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    unsigned doff[Sh::ND];  // LD: byte offset of each lane's dword of the plane tile
+    unsigned goff_int;
+    unsigned goff_h[Sh::NH];
+    int loff_h[Sh::NH];   // LDS slot of each halo load (dummy cell if unused)
+    unsigned lane_o;      // byte offset of the output point in a state plane
+    unsigned lane_w;      // byte offset of the output point in a w plane
+    unsigned plane_bytes, wplane_bytes;
+};
+
+// Addressing of the tile with corner (x0, y0).  The periodic boundary
+// condition (Sec. 4) is resolved here: a halo cell outside the interior reads
+// its periodic image, so the sweep kernels neither read nor need the ghost
+// zone.  Cells beyond x < nx + 3, y < ny + 3 never feed a stored point and are
+// dropped.
+template <typename T, typename TW, int TX, int TY, bool LD>
+__device__ __forceinline__ void sweep_ctx_init(SweepCtx<T, TX, TY, LD>& X, const Geom& g, int x0,
+                                               int y0) {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    X.plane_bytes = (unsigned)(g.plane * (long long)sizeof(T));
+    X.wplane_bytes = (unsigned)(g.wplane * (long long)sizeof(TW));
+    auto wrapped_off = [&](int gx, int gy) -> unsigned {  // gx, gy in [-3, ...)
+        if (gx >= g.nx + kR || gy >= g.ny + kR) return kDropOffset;
+        const int ix = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+        const int iy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+        return (unsigned)(((iy + kR) * g.px + (ix + kR)) * (int)sizeof(T));
+    };
+    if constexpr (LD) {
+        // dword d = 64 j + lane of the padded plane tile, j = wave + js NW
+        const int lane = threadIdx.x & 63, wv = threadIdx.x / 64;
+#pragma unroll
+        for (int js = 0; js < Sh::ND; ++js) {
+            const int d = 64 * (wv + js * Sh::NW) + lane;
+            const int e = d / Sh::DPE, half = d % Sh::DPE;
+            const int r = e / Sh::W, c = e - (e / Sh::W) * Sh::W;
+            const unsigned o = e < Sh::PLANE ? wrapped_off(x0 - kR + c, y0 - kR + r) : kDropOffset;
+            X.doff[js] = o == kDropOffset ? kDropOffset : o + 4u * (unsigned)half;
+        }
+    }
+    X.goff_int = wrapped_off(x0 + tx, y0 + ty);
+#pragma unroll
+    for (int h = 0; h < Sh::NH; ++h) {
+        const int e = threadIdx.x + h * Sh::NT;
+        int r = 0, c = 0;
+        if (e < 2 * kR * Sh::W) {
+            const int row = e / Sh::W;
+            r = row < kR ? row : row + TY;
+            c = e - row * Sh::W;
+        } else {
+            const int e2 = e - 2 * kR * Sh::W;
+            r = kR + e2 / (2 * kR);
+            const int cc = e2 % (2 * kR);
+            c = cc < kR ? cc : cc + TX;
+        }
+        const bool in_range = e < Sh::HALO;
+        X.goff_h[h] = in_range ? wrapped_off(x0 - kR + c, y0 - kR + r) : kDropOffset;
+        X.loff_h[h] = in_range ? r * Sh::W + c : Sh::PLANE;
+    }
+    const int xo = x0 + tx, yo = y0 + ty;
+    const bool store = xo < g.nx && yo < g.ny;
+    X.lane_o = store ? (unsigned)(((yo + kR) * g.px + (xo + kR)) * (int)sizeof(T)) : kDropOffset;
+    X.lane_w = store ? (unsigned)((yo * g.wpx + xo) * (int)sizeof(TW)) : kDropOffset;
+}
+
+// Workgroup index -> (tile x, tile y, z chunk): consecutive tiles (x fastest,
+// then y, then chunk) go to one XCD, which receives every 8th workgroup.
+struct SweepGrid {
+    int ntx, nty, zlen, blocks;
+};
+
+inline SweepGrid sweep_grid(const Geom& g, int tx, int ty) {
+    SweepGrid s;
+    s.ntx = (g.nx + tx - 1) / tx;
+    s.nty = (g.ny + ty - 1) / ty;
+    const long long tiles = (long long)s.ntx * s.nty;
+    // enough workgroups to fill 256 CUs several times over; z chunks cost 6
+    // extra planes of loads each, so keep them at least 16 planes long
+    const long long want = 2048;
+    int nch = (int)((want + tiles - 1) / tiles);
+    const int maxch = (g.nz + 15) / 16;
+    if (nch > maxch) nch = maxch;
+    if (nch < 1) nch = 1;
+    s.zlen = (g.nz + nch - 1) / nch;
+    nch = (g.nz + s.zlen - 1) / s.zlen;
+    s.blocks = (int)(tiles * nch);
+    return s;
+}
+
+struct TileXY {
+    int tx, ty, zb, ze;
+};
+
+__device__ __forceinline__ TileXY sweep_tile_of(const Geom& g, int TX, int TY, int ntx, int nty,
+                                                int zlen, int remap) {
+    int b = blockIdx.x;
+    const int nb = gridDim.x;
+    if (remap && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int tix = b % ntx;
+    const int tiy = (b / ntx) % nty;
+    const int ch = b / (ntx * nty);
+    const int zb = ch * zlen;
+    return TileXY{tix * TX, tiy * TY, zb, min(zb + zlen, g.nz)};
+}
+
+// Kernel shapes of the z-sweep substeps.  Index 0 is the direct kernel (one
+// thread per point, taps from the ghost zone); the others are (TX, TY) column
+// tiles.  pd: how many planes ahead the register loader fetches (2 also loads
+// the RK3 register one step early); ld: the LDS-copy loader instead.
+struct TileCfg {
+    int tx, ty, pd;
+    bool ld;
+};
+constexpr TileCfg kTiles[] = {
+    {0, 0, 1, false},   {64, 4, 1, false}, {64, 8, 1, false}, {128, 4, 1, false},
+    {32, 8, 1, false},  {64, 4, 2, false}, {64, 8, 2, false}, {128, 4, 2, false},
+    {32, 8, 2, false},  {64, 8, 1, true}};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+// Calls f(std::integral_constant<int, tile>) so that f can use kTiles[tile]
+// as template arguments; returns `bad` for an out-of-range tile.
+template <int I = 0, typename R, typename F>
+R with_tile(int tile, R bad, F&& f) {
+    if constexpr (I < kNumTiles) {
+        if (tile == I) return f(std::integral_constant<int, I>{});
+        return with_tile<I + 1>(tile, bad, f);
+    } else {
+        return bad;
+    }
+}
+
+}  // namespace
+}  // namespace fd6

@@ -1,0 +1,677 @@
+// 55-point fused substep (Sec. 4.1, Algorithm 2): the right-hand side of the
+// continuity and momentum equations (Sec. 2.1) from sixth-order first, second
+// and bidiagonal mixed differences (Sec. 2.3), followed by the 2N-RK3 update
+// (Sec. 2.4) of the RK3 register w and of the output state, in one pass.
+//
+// Kernel design for gfx950 (the paper's K40 shared-memory cube and rolling
+// cache are not reused):
+//
+//  * One workgroup owns a TX x TY column tile of the xy-plane and sweeps a
+//    chunk of z.  Each step loads one new xy-plane (tile + 3-cell halo) of the
+//    four fields from HBM into LDS (coalesced x-rows, double buffered, one
+//    barrier per plane), prefetching the next plane into registers.
+//  * From that plane every thread forms, for its own column, the x and y
+//    first derivatives of all fields and the xy part of the linear viscous
+//    term (second derivatives along x and y, xy mixed derivative).
+//  * z derivatives come from a register queue holding the thread's column
+//    over 7 planes.
+//  * The xz and yz mixed derivatives are built by scatter: the bidiagonal
+//    stencil at output plane z is sum_k c_k [A_k(z+k) - A_k(z-k)], where
+//    A_k(p) = f(x+k, p) - f(x-k, p) is the same x (or y) difference the plane
+//    step already forms, so each plane adds +-c_k A_k into pending
+//    accumulators of the output planes p -+ k (a register ring of 8 planes).
+//  * Output plane z is finished 3 planes behind the load front: the right-hand
+//    side is assembled in registers and the RK3 update is written out.
+//  * The z loop is unrolled by 8 so every ring index is a compile-time
+//    register; the workgroup-to-tile map keeps neighbouring tiles on one XCD
+//    so y-halo rows are served from that XCD's L2.
+#pragma once
+
+#include "sweep_common.hpp"
+
+namespace fd6 {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Shared per-point pieces
+// ---------------------------------------------------------------------------
+
+// Right-hand side from the derivatives at one point (eqs. continuity,
+// navierstokes with f = 0, tensor):
+//   u: centre velocity, g = grad lnrho, J[i][a] = d_a u_i,
+//   L[i] = nu (lap u_i + (1/3) d_i div u) (already scaled by nu).
+template <typename T>
+__device__ __forceinline__ void assemble_rhs(const T u[3], const T g[3], const T J[3][3],
+                                             const T L[3], T nu, T cs2, T r[4]) {
+    const T div = J[0][0] + J[1][1] + J[2][2];
+    r[0] = -(u[0] * g[0] + u[1] * g[1] + u[2] * g[2]) - div;
+    // 2 S = J + J^T - (2/3) div I, and 2 nu S . grad lnrho = nu (2S) g
+    const T d23 = div * T(2.0 / 3.0);
+    const T s01 = J[0][1] + J[1][0], s02 = J[0][2] + J[2][0], s12 = J[1][2] + J[2][1];
+    const T s00 = T(2) * J[0][0] - d23, s11 = T(2) * J[1][1] - d23, s22 = T(2) * J[2][2] - d23;
+    const T sg[3] = {s00 * g[0] + s01 * g[1] + s02 * g[2], s01 * g[0] + s11 * g[1] + s12 * g[2],
+                     s02 * g[0] + s12 * g[1] + s22 * g[2]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T adv = u[0] * J[i][0] + u[1] * J[i][1] + u[2] * J[i][2];
+        r[1 + i] = (L[i] + nu * sg[i]) - cs2 * g[i] - adv;
+    }
+}
+
+// 2N-RK3 update of one value (eq. 2N-RK_scheme, Algorithm 2):
+//   w <- alpha w + dt r  (alpha(1) = 0: substep 1 does not read w)
+//   out <- in + beta w   (substep 3 need not store w: the next step's
+//                         substep 1 ignores it)
+template <int S, typename T, typename TW>
+__device__ __forceinline__ T rk_update(T in, T r, TW& w, const RKCoef<TW>& rk) {
+    TW wn;
+    if constexpr (S == 1)
+        wn = rk.dt * TW(r);
+    else
+        wn = rk.alpha * w + rk.dt * TW(r);
+    w = wn;
+    return T(TW(in) + rk.beta * wn);
+}
+
+// ---------------------------------------------------------------------------
+// Direct kernel: one thread per point, every tap read from global memory.
+// Kept as the simplest statement of the per-point arithmetic.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T d1_at(const T* f, long long c, long long s, const T* w) {
+    return w[0] * (f[c + s] - f[c - s]) + w[1] * (f[c + 2 * s] - f[c - 2 * s]) +
+           w[2] * (f[c + 3 * s] - f[c - 3 * s]);
+}
+
+template <typename T>
+__device__ __forceinline__ T d2w_at(const T* f, long long c, long long s, const T* w) {
+    return w[0] * f[c] + w[1] * (f[c + s] + f[c - s]) + w[2] * (f[c + 2 * s] + f[c - 2 * s]) +
+           w[3] * (f[c + 3 * s] + f[c - 3 * s]);
+}
+
+template <typename T>
+__device__ __forceinline__ T mix_at(const T* f, long long c, long long sa, long long sb,
+                                    const T* w) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        const T t = (f[c + k * sa + k * sb] - f[c - k * sa + k * sb]) +
+                    (f[c - k * sa - k * sb] - f[c + k * sa - k * sb]);
+        acc += w[k - 1] * t;
+    }
+    return acc;
+}
+
+template <typename T, typename TW, int S>
+__global__ __launch_bounds__(256) void substep55_direct(Geom g, Fields4<T> in, Fields4<T> out,
+                                                        Fields4<TW> w, Coef<T> cf,
+                                                        RKCoef<TW> rk) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int k = blockIdx.z;
+    if (i >= g.nx || j >= g.ny) return;
+    const long long c = g.origin + (long long)k * g.plane + (long long)j * g.px + i;
+    const long long s[3] = {1, g.px, g.plane};
+    T gr[3], J[3][3], L[3], u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gr[a] = d1_at(in.f[0], c, s[a], cf.d1[a]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        u[q] = in.f[1 + q][c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) J[q][a] = d1_at(in.f[1 + q], c, s[a], cf.d1[a]);
+    }
+    // L_i = sum_a lw[i][a] . D2_a u_i + (1/3) sum_{j != i} D_ij u_j (nu folded)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) acc += d2w_at(in.f[1 + q], c, s[a], cf.lw[q][a]);
+        L[q] = acc;
+    }
+    L[0] += mix_at(in.f[2], c, s[0], s[1], cf.mw[0]) + mix_at(in.f[3], c, s[0], s[2], cf.mw[1]);
+    L[1] += mix_at(in.f[1], c, s[0], s[1], cf.mw[0]) + mix_at(in.f[3], c, s[1], s[2], cf.mw[2]);
+    L[2] += mix_at(in.f[1], c, s[0], s[2], cf.mw[1]) + mix_at(in.f[2], c, s[1], s[2], cf.mw[2]);
+    T r[4];
+    assemble_rhs(u, gr, J, L, cf.nu, cf.cs2, r);
+    const long long cw = (long long)k * g.wplane + (long long)j * g.wpx + i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        TW wv = (S == 1) ? TW(0) : w.f[q][cw];
+        out.f[q][c] = rk_update<S>(in.f[q][c], r[q], wv, rk);
+        if (S != 3) w.f[q][cw] = wv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z-sweep kernel
+// ---------------------------------------------------------------------------
+
+template <typename T, typename TW, int NH>
+struct SweepRegs {
+    T q[4][8];       // raw column values of the 4 fields, ring over planes
+    T L[3][8];       // pending linear viscous term of the 3 momentum components
+    T dd[4][8];      // x/y first derivatives of the 4 fields, ring of 4 planes
+    T pf[2][4];      // prefetched interior values of the next plane(s)
+    T ph[2][NH][4];  // prefetched halo values of the next plane(s)
+    TW wq[2][4];     // RK3 register of the output point (PD = 2: loaded a step early)
+};
+
+// Loads plane `corner` of the four fields (this thread's cells) into
+// register set `rs`.
+template <int RS, typename T, typename TW, int TX, int TY, int NH>
+__device__ __forceinline__ void sweep_prefetch(SweepRegs<T, TW, NH>& R,
+                                               const SweepCtx<T, TX, TY>& X,
+                                               const Fields4<T>& in, long long corner) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, X.plane_bytes);
+        R.pf[RS][f] = bload((T*)nullptr, rs, X.goff_int);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) R.ph[RS][h][f] = bload((T*)nullptr, rs, X.goff_h[h]);
+    }
+}
+
+template <int RS, typename T, typename TW, int NH>
+__device__ __forceinline__ void load_w(SweepRegs<T, TW, NH>& R, const Fields4<TW>& w,
+                                       const Geom& g, int o, unsigned wplane_bytes,
+                                       unsigned lane_w) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+        R.wq[RS][f] = bload((TW*)nullptr,
+                            plane_rsrc(w.f[f] + (long long)o * g.wplane, wplane_bytes), lane_w);
+}
+
+// LD: copy plane `corner` of the four fields into one LDS buffer.  Chunk j
+// (64 dwords) is issued by wave j % NW; its lanes fetch the dwords whose byte
+// offsets were precomputed in doff (periodic images included).
+template <typename T, int TX, int TY>
+__device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
+                                          const Fields4<T>& in, long long corner, lds_t<T> buf) {
+    using Sh = SweepShape<T, TX, TY, true>;
+    const int wv = threadIdx.x / 64;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, X.plane_bytes);
+#pragma unroll
+        for (int js = 0; js < Sh::ND; ++js) {
+            const int j = wv + js * Sh::NW;
+            if (j < Sh::NCH) {
+                lds_t<T> dst = buf + f * Sh::FS + j * (64 / Sh::DPE);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rs, (__attribute__((address_space(3))) void*)dst, 4, X.doff[js], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int PH, int S, int PD, bool LD, bool P19, typename T, typename TW, int TX, int TY,
+          int NH>
+__device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, TW, NH>& R,
+                                           const SweepCtx<T, TX, TY, LD>& X, T* lds,
+                                           lds_t<T> lds3, const Geom& g, const Fields4<T>& in,
+                                           const Fields4<T>& out, const Fields4<TW>& w, T* dv,
+                                           const Coef<T>& cf, const RKCoef<TW>& rk) {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    constexpr int W = Sh::W;
+    const int t = t0 + PH;
+    if (t >= nplanes) return;
+    const int p = zb - kR + t;  // plane loaded in this step
+    const int o = p - kR;       // output plane finished in this step
+    const bool outstep = t >= 2 * kR;
+
+    T* buf = lds + (PH & 1) * 4 * Sh::FS;
+    const int ci = (threadIdx.x / TX + kR) * W + (threadIdx.x % TX + kR);
+    // register sets: plane p sits in set RS; the RK3 register of output o in
+    // set WS
+    constexpr int RS = PD == 2 ? (PH & 1) : 0;
+    constexpr int WS = PD == 2 ? (PH & 1) : 0;
+    if constexpr (!LD) {
+        // RK3 register of an output point, issued early: PD = 1 loads the one
+        // finished in this step, PD = 2 the one finished in the next step
+        if constexpr (S != 1) {
+            if constexpr (PD == 2) {
+                if (t + 1 >= 2 * kR && t + 1 < nplanes)
+                    load_w<(PH + 1) & 1>(R, w, g, o + 1, X.wplane_bytes, X.lane_w);
+            } else {
+                if (outstep) load_w<0>(R, w, g, o, X.wplane_bytes, X.lane_w);
+            }
+        }
+        // prefetched plane p -> LDS buffer (PH & 1)
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            buf[f * Sh::FS + ci] = R.pf[RS][f];
+#pragma unroll
+            for (int h = 0; h < NH; ++h) buf[f * Sh::FS + X.loff_h[h]] = R.ph[RS][h][f];
+        }
+        // plane p + PD -> the register set just emptied
+        if (t + PD < nplanes) sweep_prefetch<RS>(R, X, in, plane_corner(g, p + PD));
+        __syncthreads();
+    } else {
+        // this wave's copies of plane p are complete before the barrier; after
+        // it the other buffer (read in the previous step by every wave) takes
+        // plane p + 1
+        __syncthreads();
+        if (t + 1 < nplanes)
+            sweep_dma<T, TX, TY>(X, in, plane_corner(g, p + 1), lds3 + ((PH + 1) & 1) * 4 * Sh::FS);
+        if constexpr (S != 1) {
+            if (outstep) load_w<0>(R, w, g, o, X.wplane_bytes, X.lane_w);
+        }
+    }
+
+    // ---- plane quantities of plane p for this thread's column ----
+    // Stencils use their integer weights; grid spacing and viscosity enter
+    // through per-axis scale factors (see Coef), which keeps the runtime
+    // constants few enough to stay in scalar registers.
+    // all taps as non-negative constant offsets from one window base
+    const T* win = buf + (ci - kR * W - kR);
+    constexpr int C0 = kR * W + kR;  // centre of the window
+    const T* B0 = win + C0;
+    const T* B1 = win + Sh::FS + C0;
+    const T* B2 = win + 2 * Sh::FS + C0;
+    const T* B3 = win + 3 * Sh::FS + C0;
+    constexpr int DS = PH & 3;  // first-derivative slot of plane p
+    constexpr T w2[3] = {T(270), T(-27), T(2)};
+
+    // (A) what output p - 3 still needs from plane p: the centre values (top
+    // of the z queues) and the k = 3 terms of its xz / yz stencils.  The
+    // first contribution to output p + 3 (from the same differences) assigns.
+    // The 19-point form has no mixed terms.
+    {
+        R.q[0][sl8(PH)] = B0[0];
+        R.q[1][sl8(PH)] = B1[0];
+        R.q[2][sl8(PH)] = B2[0];
+        R.q[3][sl8(PH)] = B3[0];
+    }
+    if constexpr (!P19) {
+        const T zs3[3] = {cf.mu[1] * (B3[3] - B3[-3]),                 // (1/3) Dxz uz
+                          cf.mu[2] * (B3[3 * W] - B3[-3 * W]),         // (1/3) Dyz uz
+                          cf.mu[1] * (B1[3] - B1[-3]) +                // (1/3) Dxz ux
+                              cf.mu[2] * (B2[3 * W] - B2[-3 * W])};    // + (1/3) Dyz uy
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            R.L[i][sl8(PH - 3)] += T(2) * zs3[i];
+            R.L[i][sl8(PH + 3)] = T(-2) * zs3[i];
+        }
+    }
+
+    // (B) finish output plane o = p - 3 before the rest of plane p is formed,
+    // so the two working sets do not overlap in registers
+    if (outstep) {
+        T dz[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+            dz[f] = cf.d1[2][0] * (R.q[f][sl8(PH - 2)] - R.q[f][sl8(PH - 4)]) +
+                    cf.d1[2][1] * (R.q[f][sl8(PH - 1)] - R.q[f][sl8(PH - 5)]) +
+                    cf.d1[2][2] * (R.q[f][sl8(PH)] - R.q[f][sl8(PH - 6)]);
+        T Lf[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int f = 1 + i;
+            const T rz = T(270) * (R.q[f][sl8(PH - 2)] + R.q[f][sl8(PH - 4)]) +
+                         T(-27) * (R.q[f][sl8(PH - 1)] + R.q[f][sl8(PH - 5)]) +
+                         T(2) * (R.q[f][sl8(PH)] + R.q[f][sl8(PH - 6)]) +
+                         T(-490) * R.q[f][sl8(PH - 3)];
+            Lf[i] = R.L[i][sl8(PH - 3)] + ((i == 2 && !P19) ? cf.sg4[2] : cf.sg[2]) * rz;
+        }
+        constexpr int DO = (PH + 1) & 3;  // slot of plane p - 3
+        const T gr[3] = {R.dd[DO][0], R.dd[DO][1], dz[0]};
+        const T J[3][3] = {{R.dd[DO][2], R.dd[DO][3], dz[1]},
+                           {R.dd[DO][4], R.dd[DO][5], dz[2]},
+                           {R.dd[DO][6], R.dd[DO][7], dz[3]}};
+        const T u[3] = {R.q[1][sl8(PH - 3)], R.q[2][sl8(PH - 3)], R.q[3][sl8(PH - 3)]};
+        T r[4];
+        assemble_rhs(u, gr, J, Lf, cf.nu, cf.cs2, r);
+        // ghost corner (-3, -3) of output plane o
+        const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            TW wv = S == 1 ? TW(0) : R.wq[WS][f];
+            const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv, rk);
+            bstore(v, plane_rsrc(out.f[f] + ocorner, X.plane_bytes), X.lane_o);
+            if constexpr (S != 3)
+                bstore(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes),
+                       X.lane_w);
+        }
+        // 19-point pass 1 also stores the divergence for pass 2
+        if constexpr (P19)
+            bstore(J[0][0] + J[1][1] + J[2][2], plane_rsrc(dv + ocorner, X.plane_bytes),
+                   X.lane_o);
+    }
+
+    // (C) the rest of plane p for this column: x / y first derivatives of the
+    // four fields (kept 3 planes), the xy part of the linear viscous term, and
+    // the k = 1, 2 terms of the xz / yz stencils of outputs p -+ k.
+    // lnrho
+    R.dd[DS][0] = cf.d1[0][0] * (B0[1] - B0[-1]) + cf.d1[0][1] * (B0[2] - B0[-2]) +
+                  cf.d1[0][2] * (B0[3] - B0[-3]);
+    R.dd[DS][1] = cf.d1[1][0] * (B0[W] - B0[-W]) + cf.d1[1][1] * (B0[2 * W] - B0[-2 * W]) +
+                  cf.d1[1][2] * (B0[3 * W] - B0[-3 * W]);
+    T lx, ly, lz;  // xy parts of nu (lap u_i + (1/3) d_i div u) at plane p (19-point:
+                   // of nu lap u_i)
+    T zx[2], zy[2], zz[2];  // scaled k = 1, 2 differences feeding the xz / yz terms
+    // ux
+    {
+        const T c = B1[0];
+        T a[3], b[3];
+        T rx = T(0), ry = T(0), m = T(0);
+#pragma unroll
+        for (int k = 1; k <= 3; ++k) {
+            const T xp = B1[k], xm = B1[-k], yp = B1[k * W], ym = B1[-k * W];
+            a[k - 1] = xp - xm;
+            b[k - 1] = yp - ym;
+            rx += w2[k - 1] * (xp + xm);
+            ry += w2[k - 1] * (yp + ym);
+            if constexpr (!P19) {
+                const T t = (B1[k * W + k] - B1[k * W - k]) + (B1[-k * W - k] - B1[-k * W + k]);
+                m += w2[k - 1] * t;
+            }
+        }
+        R.dd[DS][2] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
+        R.dd[DS][3] = cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2];
+        if constexpr (P19) {
+            lx = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+            ly = T(0);
+        } else {
+            lx = cf.kxy[0] * c + cf.sg4[0] * rx + cf.sg[1] * ry;  // (4/3) D2x + D2y
+            ly = cf.mu[0] * m;                                     // (1/3) Dxy ux
+        }
+        if constexpr (!P19) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) zz[k] = cf.mu[1] * a[k];  // (1/3) Dxz ux
+        }
+    }
+    // uy
+    {
+        const T c = B2[0];
+        T a[3], b[3];
+        T rx = T(0), ry = T(0), m = T(0);
+#pragma unroll
+        for (int k = 1; k <= 3; ++k) {
+            const T xp = B2[k], xm = B2[-k], yp = B2[k * W], ym = B2[-k * W];
+            a[k - 1] = xp - xm;
+            b[k - 1] = yp - ym;
+            rx += w2[k - 1] * (xp + xm);
+            ry += w2[k - 1] * (yp + ym);
+            if constexpr (!P19) {
+                const T t = (B2[k * W + k] - B2[k * W - k]) + (B2[-k * W - k] - B2[-k * W + k]);
+                m += w2[k - 1] * t;
+            }
+        }
+        R.dd[DS][4] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
+        R.dd[DS][5] = cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2];
+        if constexpr (P19) {
+            ly = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+        } else {
+            ly += cf.kxy[1] * c + cf.sg[0] * rx + cf.sg4[1] * ry;  // D2x + (4/3) D2y
+            lx += cf.mu[0] * m;                                     // (1/3) Dxy uy
+        }
+        if constexpr (!P19) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) zz[k] += cf.mu[2] * b[k];  // (1/3) Dyz uy
+        }
+    }
+    // uz
+    {
+        const T c = B3[0];
+        T a[3], b[3];
+        T rx = T(0), ry = T(0);
+#pragma unroll
+        for (int k = 1; k <= 3; ++k) {
+            const T xp = B3[k], xm = B3[-k], yp = B3[k * W], ym = B3[-k * W];
+            a[k - 1] = xp - xm;
+            b[k - 1] = yp - ym;
+            rx += w2[k - 1] * (xp + xm);
+            ry += w2[k - 1] * (yp + ym);
+        }
+        R.dd[DS][6] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
+        R.dd[DS][7] = cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2];
+        lz = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+        if constexpr (!P19) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                zx[k] = cf.mu[1] * a[k];  // (1/3) Dxz uz
+                zy[k] = cf.mu[2] * b[k];  // (1/3) Dyz uy
+            }
+        }
+    }
+
+    // Scatter: the bidiagonal xz / yz stencil at output z is
+    // sum_k c_k [A_k(z + k) - A_k(z - k)], so plane p adds +c_k A_k to the
+    // pending output p - k and -c_k A_k to p + k (c = 270, -27, 2); the k = 3
+    // terms were added in (A).
+    if constexpr (P19) {
+        R.L[0][sl8(PH)] = lx;
+        R.L[1][sl8(PH)] = ly;
+        R.L[2][sl8(PH)] = lz;
+    } else {
+        const T* zs[3] = {zx, zy, zz};
+        const T lc[3] = {lx, ly, lz};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            R.L[i][sl8(PH + 2)] += T(27) * zs[i][1];
+            R.L[i][sl8(PH + 1)] += T(-270) * zs[i][0];
+            R.L[i][sl8(PH)] += lc[i];
+            R.L[i][sl8(PH - 1)] += T(270) * zs[i][0];
+            R.L[i][sl8(PH - 2)] += T(-27) * zs[i][1];
+        }
+    }
+}
+
+// One tile-chunk: columns [x0, x0 + TX) x [y0, y0 + TY) of the box, output
+// planes [zb, ze).  Every thread of the workgroup calls it with the same
+// arguments.  P19: pass 1 of the 19-point method (dv receives the divergence).
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool P19 = false>
+__device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
+                                           const Fields4<T>& out, const Fields4<TW>& w, T* dv,
+                                           const Coef<T>& cf, const RKCoef<TW>& rk, int x0,
+                                           int y0, int zb, int ze, T* lds, lds_t<T> lds3) {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    constexpr int NH = Sh::NH;
+    SweepCtx<T, TX, TY, LD> X;
+    sweep_ctx_init<T, TW, TX, TY, LD>(X, g, x0, y0);
+
+    SweepRegs<T, TW, NH> R;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            R.q[f][s] = T(0);
+            R.dd[s >> 1][(2 * f + (s & 1))] = T(0);
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) R.L[i][s] = T(0);
+
+    const int nplanes = (ze - zb) + 2 * kR;
+    if constexpr (LD) {
+        sweep_dma<T, TX, TY>(X, in, plane_corner(g, zb - kR), lds3);
+    } else {
+        sweep_prefetch<0>(R, X, in, plane_corner(g, zb - kR));
+        if constexpr (PD == 2) sweep_prefetch<1>(R, X, in, plane_corner(g, zb - kR + 1));
+    }
+    for (int t0 = 0; t0 < nplanes; t0 += 8) {
+        sweep_step<0, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<1, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<2, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<3, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<4, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<5, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<6, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<7, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+    }
+}
+
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD>
+__global__ __launch_bounds__(TX* TY)
+void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
+                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap) {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    __shared__ T lds[2 * 4 * Sh::FS];
+    const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    if (t.zb >= t.ze) return;
+    sweep_tile<T, TW, TX, TY, S, PD, LD>(g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds,
+                                     (lds_t<T>)lds);
+}
+
+// Pass 1 of the 19-point method (Sec. 4.2, Algorithm 3): the same sweep
+// without the mixed-derivative terms, with nu lap u in place of the viscous
+// operator, and the divergence stored for pass 2.
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD>
+__global__ __launch_bounds__(TX* TY)
+void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv, Coef<T> cf,
+                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap) {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    __shared__ T lds[2 * 4 * Sh::FS];
+    const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    if (t.zb >= t.ze) return;
+    sweep_tile<T, TW, TX, TY, S, PD, LD, true>(g, in, out, w, dv, cf, rk, t.tx, t.ty, t.zb, t.ze,
+                                           lds, (lds_t<T>)lds);
+}
+
+// Batched form: one persistent launch advances every box of an ensemble by
+// one substep.  The host lists the tile-chunks of all boxes (longest first);
+// workgroup b takes list entries remap(b), remap(b) + G, ... where the remap
+// gives each XCD a contiguous run of the list, so that tiles of one box share
+// that XCD's L2.  Per-box geometry, pointers, coefficients and time step come
+// from device memory, so a captured graph never needs re-capture when they
+// change.  Per point the arithmetic is the single-box kernel's.
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD>
+__global__ __launch_bounds__(TX* TY)
+void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
+                     const BatchItem* __restrict__ items, int nitems, int parity, TW alpha,
+                     TW beta) {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    __shared__ T lds[2 * 4 * Sh::FS];
+    const int G = gridDim.x;
+    int b = blockIdx.x;
+    if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
+    for (int it = b; it < nitems; it += G) {
+        const BatchItem wi = items[it];
+        const BatchBox<T, TW>* bx = boxes + wi.box;
+        const Geom g = bx->g;
+        const Coef<T> cf = bx->cf;
+        const Fields4<T> in = bx->st[parity], out = bx->st[parity ^ 1];
+        const Fields4<TW> w = bx->w;
+        const RKCoef<TW> rk{alpha, beta, bx->dt};
+        sweep_tile<T, TW, TX, TY, S, PD, LD>(g, in, out, w, nullptr, cf, rk, wi.x0, wi.y0, wi.zb,
+                                         wi.ze, lds, (lds_t<T>)lds);
+        __syncthreads();  // the next item's first LDS write must follow every read
+    }
+}
+
+// Launch helpers: the substep index S is a template argument of every kernel.
+template <template <int> class K, typename... A>
+hipError_t launch_s(int s, dim3 grid, dim3 block, hipStream_t st, A... args) {
+    switch (s) {
+    case 1: hipLaunchKernelGGL(K<1>::fn, grid, block, 0, st, args...); break;
+    case 2: hipLaunchKernelGGL(K<2>::fn, grid, block, 0, st, args...); break;
+    default: hipLaunchKernelGGL(K<3>::fn, grid, block, 0, st, args...); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+struct K55 {
+    template <int S>
+    struct at {
+        static constexpr auto fn = substep55_sweep<T, TW, TX, TY, S, PD, LD>;
+    };
+};
+template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+struct K19 {
+    template <int S>
+    struct at {
+        static constexpr auto fn = substep19_pass1<T, TW, TX, TY, S, PD, LD>;
+    };
+};
+template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+struct KBatch {
+    template <int S>
+    struct at {
+        static constexpr auto fn = substep55_batch<T, TW, TX, TY, S, PD, LD>;
+    };
+};
+template <typename T, typename TW>
+struct KDirect {
+    template <int S>
+    struct at {
+        static constexpr auto fn = substep55_direct<T, TW, S>;
+    };
+};
+
+}  // namespace
+
+
+template <typename T, typename TW>
+hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                            hipStream_t st) {
+    return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
+        constexpr TileCfg k = kTiles[decltype(I)::value];
+        if constexpr (k.tx == 0) {
+            const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4),
+                            (unsigned)g.nz);
+            return launch_s<KDirect<T, TW>::template at>(s, grid, dim3(256), st, g, in, out, w,
+                                                         c, rk);
+        } else {
+            const SweepGrid sg = sweep_grid(g, k.tx, k.ty);
+            return launch_s<K55<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
+                s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in, out, w, c, rk, sg.ntx, sg.nty,
+                sg.zlen, xcd_remap());
+        }
+    });
+}
+
+// Pass 1 of the 19-point method in a z-sweep shape (tile >= 1).
+template <typename T, typename TW>
+hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                                T* dv, const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                                hipStream_t st) {
+    return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
+        constexpr TileCfg k = kTiles[decltype(I)::value];
+        if constexpr (k.tx == 0) {
+            return hipErrorInvalidValue;
+        } else {
+            const SweepGrid sg = sweep_grid(g, k.tx, k.ty);
+            return launch_s<K19<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
+                s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in, out, w, dv, c, rk, sg.ntx,
+                sg.nty, sg.zlen, xcd_remap());
+        }
+    });
+}
+
+template <typename T, typename TW>
+hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                          int grid, int parity, int s, int tile, TW alpha, TW beta,
+                          hipStream_t st) {
+    return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
+        constexpr TileCfg k = kTiles[decltype(I)::value];
+        if constexpr (k.tx == 0) {
+            return hipErrorInvalidValue;
+        } else {
+            return launch_s<KBatch<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
+                s, dim3(grid), dim3(k.tx * k.ty), st, boxes, items, nitems, parity, alpha, beta);
+        }
+    });
+}
+
+template <typename T, typename TW>
+int batch55_blocks_per_cu(int tile) {
+    return with_tile(tile, 1, [&](auto I) -> int {
+        constexpr TileCfg k = kTiles[decltype(I)::value];
+        if constexpr (k.tx == 0) {
+            return 1;
+        } else {
+            int n = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &n, substep55_batch<T, TW, k.tx, k.ty, 2, k.pd, k.ld>, k.tx * k.ty, 0) !=
+                hipSuccess)
+                return 1;
+            return n > 0 ? n : 1;
+        }
+    });
+}
+
+}  // namespace fd6

@@ -1,4 +1,4 @@
-"""Autotuner for the 55-point substep kernel shape.
+"""Autotuner for the substep kernel shape (55-point and 19-point methods).
 
 Times every kernel shape the library offers (fd6_tile_count) on the caller's
 own box with HIP events, keeps the fastest, and caches the choice in a JSON
@@ -58,8 +58,6 @@ def tune(box: Box, steps: int = 3, use_cache: bool = True,
     if use_cache and key in cache:
         box.set_tile(cache[key]["tile"])
         return cache[key]
-    if box.variant != "55p":
-        return {"tile": 0, "ms": None, "timings": {}}
     tiles = candidates if candidates is not None else list(range(1, tile_count()))
     timings = {t: time_tile(box, t, steps) for t in tiles}
     best = min(timings, key=timings.get)

@@ -89,14 +89,39 @@ def test_ragged_shapes_fp64(fd6, orc, shape):
         assert e <= 1e-12, (shape, tile, e)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_19p_variant(fd6, orc, precision):
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_acc64"])
+def test_19p_variant_all_kernels(fd6, orc, precision):
+    """Both passes of the 19-point method in every kernel shape: the direct
+    kernels (ghost zones) and the z-sweeps (periodic images in the loader)."""
     w = si.small_parity_box(seed=1)
     ref = run_oracle(orc, w, precision, variant="19p")
-    out = run_gpu(fd6, w, precision, variant="19p")
-    e = rel_err(out, ref)
-    print(f"19p {precision}: {e:.3e}", flush=True)
-    assert e <= TOL[precision]
+    errs = {}
+    for tile in range(fd6.tile_count()):
+        out = run_gpu(fd6, w, precision, variant="19p", tile=tile)
+        errs[tile] = rel_err(out, ref)
+        print(f"19p {precision} tile {tile}: {errs[tile]:.3e}", flush=True)
+    assert max(errs.values()) <= TOL[precision], errs
+
+
+@pytest.mark.parametrize("shape", [(23, 29, 37), (6, 6, 6), (9, 11, 13), (40, 6, 130)])
+def test_19p_ragged_and_wrapped_fp64(fd6, orc, shape):
+    """Tails, the minimum size and boxes smaller than a tile (every halo cell
+    is a periodic image), several steps."""
+    w = si.noise_box(shape, seed=15)
+    ref = run_oracle(orc, w, "fp64", variant="19p", nsteps=3)
+    for tile in range(fd6.tile_count()):
+        e = rel_err(run_gpu(fd6, w, "fp64", variant="19p", nsteps=3, tile=tile), ref)
+        print(f"19p {shape} tile {tile}: {e:.3e}", flush=True)
+        assert e <= 1e-12, (shape, tile, e)
+
+
+def test_19p_sweep_tiles_are_bitwise_identical(fd6):
+    w = si.noise_box((20, 21, 70), seed=18)
+    outs = [run_gpu(fd6, w, "fp32", variant="19p", nsteps=2, tile=t)
+            for t in range(1, fd6.tile_count())]
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
 
 
 def test_mid_box_several_steps_fp64(fd6, orc):
@@ -139,9 +164,11 @@ def test_rest_state_bitwise(fd6):
 
 
 @pytest.mark.parametrize("variant", ["55p", "19p"])
-def test_rhs_hook_fp64(fd6, orc, variant):
+@pytest.mark.parametrize("tile", [0, 4])
+def test_rhs_hook_fp64(fd6, orc, variant, tile):
     w = si.noise_box((18, 20, 22), seed=4)
     box = fd6.Box(w.shape, "fp64", variant)
+    box.set_tile(tile)
     box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
     box.init_fields(w.fields)
     r = box.rhs()
