@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for rocprofv3)")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="kernel shape of the headline run (skips the autotuner)")
     a = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -213,18 +215,28 @@ def main():
     w = si.large_box(n)
     log(f"inputs {n}^3 generated in {time.perf_counter() - t0:.1f} s; dt = {w.dt:.4e}")
 
-    if a.calibrate_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # streaming reference: a plain 1 GiB device-to-device copy (also the
+    # calibration kernel of the rocprofv3 traffic counters)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3 if a.calibrate_copy else 5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 2 * src.numel() * 4 * (3 if a.calibrate_copy else 5) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    log(f"device copy 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
 
     dev_fields = [torch.from_numpy(f).cuda() for f in w.fields]
     red = torch.zeros(8, dtype=torch.float64, device="cuda")
-    box, tuned = make_box(fd6, w, dev_fields, "fp32", "55p")
-    log(f"tuned kernel shape: {tuned}")
+    box, tuned = make_box(fd6, w, dev_fields, "fp32", "55p", tune=a.tile is None)
+    if a.tile is not None:
+        box.set_tile(a.tile)
+        tuned = {"tile": a.tile}
+    log(f"kernel shape: {tuned}")
     wall, ev_ms, (kms, klaunch, gms, glaunch) = timed_steps(torch, box, red, a.steps, a.warmup)
     r = red.cpu().numpy()
     box.close()
@@ -244,7 +256,8 @@ def main():
                 "kernel": "substep55_sweep (fused RHS + RK3)",
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": klaunch,
                 "alg_bytes_per_launch": alg_per_launch,
-                "ghost_fill_us_per_launch": round(gms * 1e3 / max(glaunch, 1), 2)}
+                "ghost_fill_us_per_launch": round(gms * 1e3 / max(glaunch, 1), 2),
+                "device_copy_gbs": round(copy_gbs, 1)}
 
     import oracle
     forms = {}

@@ -121,11 +121,13 @@ struct Pass2Regs {
     T ph[NH];    // prefetched halo values of the next plane
 };
 
+// As in the 55-point sweep, no memory operation of a step sits behind a
+// branch: a step with nothing to load or store uses descriptors of zero range.
 template <typename T, int TX, int TY, int NH>
 __device__ __forceinline__ void pass2_prefetch(Pass2Regs<T, NH>& R,
                                                const SweepCtx<T, TX, TY>& X, const T* dv,
-                                               long long corner) {
-    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(dv + corner, X.plane_bytes);
+                                               long long corner, unsigned bytes) {
+    const __amdgpu_buffer_rsrc_t rs = plane_rsrc(dv + corner, bytes);
     R.pf = bload((T*)nullptr, rs, X.goff_int);
 #pragma unroll
     for (int h = 0; h < NH; ++h) R.ph[h] = bload((T*)nullptr, rs, X.goff_h[h]);
@@ -145,25 +147,24 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
     const int o = p - kR;       // output plane finished in this step
     const bool outstep = t >= 2 * kR;
     const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
+    const unsigned ob = outstep ? X.plane_bytes : 0u;
+    const unsigned wb = outstep ? X.wplane_bytes : 0u;
     T ov[3] = {T(0), T(0), T(0)};
     TW wv[3] = {TW(0), TW(0), TW(0)};
-    if (outstep) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            ov[i] = bload((T*)nullptr, plane_rsrc(out.f[1 + i] + ocorner, X.plane_bytes),
-                          X.lane_o);
-            if constexpr (S != 3)
-                wv[i] = bload((TW*)nullptr,
-                              plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, X.wplane_bytes),
-                              X.lane_w);
-        }
+    for (int i = 0; i < 3; ++i) {
+        ov[i] = bload((T*)nullptr, plane_rsrc(out.f[1 + i] + ocorner, ob), X.lane_o);
+        if constexpr (S != 3)
+            wv[i] = bload((TW*)nullptr, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, wb),
+                          X.lane_w);
     }
     T* buf = lds + (PH & 1) * Sh::FS;
     const int ci = (threadIdx.x / TX + kR) * W + (threadIdx.x % TX + kR);
     buf[ci] = R.pf;
 #pragma unroll
     for (int h = 0; h < NH; ++h) buf[X.loff_h[h]] = R.ph[h];
-    if (t + 1 < nplanes) pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, p + 1));
+    pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, p + 1),
+                                  t + 1 < nplanes ? X.plane_bytes : 0u);
     __syncthreads();
 
     const T* B = buf + ci;
@@ -172,7 +173,7 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
                    cf.d1[0][2] * (B[3] - B[-3]);
     R.dy[PH & 3] = cf.d1[1][0] * (B[W] - B[-W]) + cf.d1[1][1] * (B[2 * W] - B[-2 * W]) +
                    cf.d1[1][2] * (B[3 * W] - B[-3 * W]);
-    if (outstep) {
+    {
         const T dz = cf.d1[2][0] * (R.q[sl8(PH - 2)] - R.q[sl8(PH - 4)]) +
                      cf.d1[2][1] * (R.q[sl8(PH - 1)] - R.q[sl8(PH - 5)]) +
                      cf.d1[2][2] * (R.q[sl8(PH)] - R.q[sl8(PH - 6)]);
@@ -182,10 +183,10 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
         for (int i = 0; i < 3; ++i) {
             const TW tq = cgd * TW(gd[i]);
             if constexpr (S != 3)
-                bstore(wv[i] + tq, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, X.wplane_bytes),
+                bstore(wv[i] + tq, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, wb),
                        X.lane_w);
-            bstore(T(TW(ov[i]) + rk.beta * tq),
-                   plane_rsrc(out.f[1 + i] + ocorner, X.plane_bytes), X.lane_o);
+            bstore(T(TW(ov[i]) + rk.beta * tq), plane_rsrc(out.f[1 + i] + ocorner, ob),
+                   X.lane_o);
         }
     }
 }
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __res
     for (int s = 0; s < 4; ++s) R.dx[s] = R.dy[s] = T(0);
     const int zb = tl.zb;
     const int nplanes = (tl.ze - zb) + 2 * kR;
-    pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, zb - kR));
+    pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, zb - kR), X.plane_bytes);
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
         pass2_step<0, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
         pass2_step<1, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);

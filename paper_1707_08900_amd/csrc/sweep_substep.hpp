@@ -157,15 +157,22 @@ struct SweepRegs {
     TW wq[2][4];     // RK3 register of the output point (PD = 2: loaded a step early)
 };
 
+// Memory operations of a plane step are never skipped by a branch: a step
+// that has nothing to load or store gives its descriptors a zero range (loads
+// return 0, stores are dropped).  Branch-free memory code lets the compiler
+// count outstanding loads exactly across steps instead of draining the memory
+// pipeline (stores share the load counter on this architecture).
+
 // Loads plane `corner` of the four fields (this thread's cells) into
-// register set `rs`.
+// register set RS; bytes = 0 loads nothing.
 template <int RS, typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_prefetch(SweepRegs<T, TW, NH>& R,
                                                const SweepCtx<T, TX, TY>& X,
-                                               const Fields4<T>& in, long long corner) {
+                                               const Fields4<T>& in, long long corner,
+                                               unsigned bytes) {
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, X.plane_bytes);
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, bytes);
         R.pf[RS][f] = bload((T*)nullptr, rs, X.goff_int);
 #pragma unroll
         for (int h = 0; h < NH; ++h) R.ph[RS][h][f] = bload((T*)nullptr, rs, X.goff_h[h]);
@@ -187,12 +194,13 @@ __device__ __forceinline__ void load_w(SweepRegs<T, TW, NH>& R, const Fields4<TW
 // offsets were precomputed in doff (periodic images included).
 template <typename T, int TX, int TY>
 __device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
-                                          const Fields4<T>& in, long long corner, lds_t<T> buf) {
+                                          const Fields4<T>& in, long long corner, lds_t<T> buf,
+                                          unsigned bytes) {
     using Sh = SweepShape<T, TX, TY, true>;
     const int wv = threadIdx.x / 64;
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, X.plane_bytes);
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, bytes);
 #pragma unroll
         for (int js = 0; js < Sh::ND; ++js) {
             const int j = wv + js * Sh::NW;
@@ -231,10 +239,10 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         // finished in this step, PD = 2 the one finished in the next step
         if constexpr (S != 1) {
             if constexpr (PD == 2) {
-                if (t + 1 >= 2 * kR && t + 1 < nplanes)
-                    load_w<(PH + 1) & 1>(R, w, g, o + 1, X.wplane_bytes, X.lane_w);
+                const bool next_out = t + 1 >= 2 * kR && t + 1 < nplanes;
+                load_w<(PH + 1) & 1>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u, X.lane_w);
             } else {
-                if (outstep) load_w<0>(R, w, g, o, X.wplane_bytes, X.lane_w);
+                load_w<0>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
             }
         }
         // prefetched plane p -> LDS buffer (PH & 1)
@@ -245,17 +253,18 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             for (int h = 0; h < NH; ++h) buf[f * Sh::FS + X.loff_h[h]] = R.ph[RS][h][f];
         }
         // plane p + PD -> the register set just emptied
-        if (t + PD < nplanes) sweep_prefetch<RS>(R, X, in, plane_corner(g, p + PD));
+        sweep_prefetch<RS>(R, X, in, plane_corner(g, p + PD),
+                           t + PD < nplanes ? X.plane_bytes : 0u);
         __syncthreads();
     } else {
         // this wave's copies of plane p are complete before the barrier; after
         // it the other buffer (read in the previous step by every wave) takes
         // plane p + 1
         __syncthreads();
-        if (t + 1 < nplanes)
-            sweep_dma<T, TX, TY>(X, in, plane_corner(g, p + 1), lds3 + ((PH + 1) & 1) * 4 * Sh::FS);
+        sweep_dma<T, TX, TY>(X, in, plane_corner(g, p + 1), lds3 + ((PH + 1) & 1) * 4 * Sh::FS,
+                             t + 1 < nplanes ? X.plane_bytes : 0u);
         if constexpr (S != 1) {
-            if (outstep) load_w<0>(R, w, g, o, X.wplane_bytes, X.lane_w);
+            load_w<0>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
         }
     }
 
@@ -296,8 +305,12 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     }
 
     // (B) finish output plane o = p - 3 before the rest of plane p is formed,
-    // so the two working sets do not overlap in registers
-    if (outstep) {
+    // so the two working sets do not overlap in registers.  In the first 6
+    // steps of a chunk there is no output plane yet: the arithmetic runs on
+    // the zero-initialised rings and the stores are dropped.
+    {
+        const unsigned ob = outstep ? X.plane_bytes : 0u;
+        const unsigned wb = outstep ? X.wplane_bytes : 0u;
         T dz[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f)
@@ -328,15 +341,13 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         for (int f = 0; f < 4; ++f) {
             TW wv = S == 1 ? TW(0) : R.wq[WS][f];
             const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv, rk);
-            bstore(v, plane_rsrc(out.f[f] + ocorner, X.plane_bytes), X.lane_o);
+            bstore(v, plane_rsrc(out.f[f] + ocorner, ob), X.lane_o);
             if constexpr (S != 3)
-                bstore(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, X.wplane_bytes),
-                       X.lane_w);
+                bstore(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, wb), X.lane_w);
         }
         // 19-point pass 1 also stores the divergence for pass 2
         if constexpr (P19)
-            bstore(J[0][0] + J[1][1] + J[2][2], plane_rsrc(dv + ocorner, X.plane_bytes),
-                   X.lane_o);
+            bstore(J[0][0] + J[1][1] + J[2][2], plane_rsrc(dv + ocorner, ob), X.lane_o);
     }
 
     // (C) the rest of plane p for this column: x / y first derivatives of the
@@ -486,10 +497,11 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
 
     const int nplanes = (ze - zb) + 2 * kR;
     if constexpr (LD) {
-        sweep_dma<T, TX, TY>(X, in, plane_corner(g, zb - kR), lds3);
+        sweep_dma<T, TX, TY>(X, in, plane_corner(g, zb - kR), lds3, X.plane_bytes);
     } else {
-        sweep_prefetch<0>(R, X, in, plane_corner(g, zb - kR));
-        if constexpr (PD == 2) sweep_prefetch<1>(R, X, in, plane_corner(g, zb - kR + 1));
+        sweep_prefetch<0>(R, X, in, plane_corner(g, zb - kR), X.plane_bytes);
+        if constexpr (PD == 2)
+            sweep_prefetch<1>(R, X, in, plane_corner(g, zb - kR + 1), X.plane_bytes);
     }
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
         sweep_step<0, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
