@@ -169,6 +169,12 @@ int fd6_rhs(fd6_box *box, double *r_lnrho, double *r_ux, double *r_uy, double *r
 int fd6_tile_count(void);
 int fd6_set_tile(fd6_box *box, int32_t tile);
 
+/* Length in z-planes of the chunk one workgroup of a z-sweep kernel sweeps
+ * (each chunk re-reads 6 planes): 0 (default) lets the library choose enough
+ * workgroups to fill the device; values above nz mean whole columns.  Results
+ * do not depend on it (bit for bit).  FD6_EINVAL if zchunk < 0. */
+int fd6_set_zchunk(fd6_box *box, int32_t zchunk);
+
 /* Kernel timing with HIP events recorded on the box's stream around every
  * launch of the main substep kernel(s) (55-point fused kernel; both passes of
  * the 19-point method) and of the ghost fill.  enable != 0 starts (and

@@ -43,6 +43,7 @@ struct fd6_box {
     long long staging_elems = 0;
     int cur = 0;
     int tile = 2;  // 64 x 8 z-sweep
+    int zchunk = 0;  // z-sweep chunk length, 0: automatic
     bool ghosts_ok[2] = {false, false};  // ghost zone of each state set is current
     std::string err;
     // optional per-launch event timing
@@ -304,14 +305,16 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
     }
     if (b->desc.variant == FD6_55P) {
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->stream)));
+            HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->zchunk,
+                                               b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;
     } else {
         T* dv = static_cast<T*>(b->div);
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->tile, b->stream)));
+            HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->tile, b->zchunk,
+                                                b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;
@@ -324,7 +327,8 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
             if (rc) return rc;
         }
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, s, b->tile, b->stream)));
+            HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, s, b->tile, b->zchunk,
+                                                b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;
@@ -982,6 +986,12 @@ int fd6_set_tile(fd6_box* b, int32_t tile) {
 }
 
 int fd6_tile_count(void) { return substep55_tile_count(); }
+
+int fd6_set_zchunk(fd6_box* b, int32_t zchunk) {
+    if (!b || zchunk < 0) return FD6_EINVAL;
+    b->zchunk = zchunk;
+    return FD6_OK;
+}
 
 int fd6_batch_workspace_bytes(int32_t n, const fd6_desc* descs, size_t* bytes) {
     if (!bytes) return FD6_EINVAL;

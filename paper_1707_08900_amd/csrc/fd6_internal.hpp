@@ -93,10 +93,11 @@ hipError_t launch_export_w(const Geom& g, const TW* src, double* dst, hipStream_
 template <typename TW>
 hipError_t launch_zero_w(const Geom& g, Fields4<TW> w, hipStream_t s);
 
-// 55-point fused right-hand side + RK3 update for substep s (1, 2, 3).
+// 55-point fused right-hand side + RK3 update for substep s (1, 2, 3) with
+// kernel shape `tile` and z-chunk length `zchunk` (0: chosen by the launcher).
 template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
-                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
                             hipStream_t st);
 // Whether a kernel shape reads the ghost zone of its input (the z-sweep
 // shapes resolve the periodic images in their loader instead).
@@ -130,15 +131,15 @@ int batch55_blocks_per_cu(int tile);
 // z-sweep shapes resolve periodic images themselves.
 template <typename T, typename TW>
 hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,
-                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
                           hipStream_t st);
 template <typename T, typename TW>
 hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                                 T* div, const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
-                                hipStream_t st);
+                                int zchunk, hipStream_t st);
 template <typename T, typename TW>
 hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
-                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
                           hipStream_t st);
 
 // FP64 reductions: per-block partials then one fixed-order final block.

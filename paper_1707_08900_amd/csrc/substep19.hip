@@ -228,9 +228,10 @@ __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __res
 
 template <typename T, typename TW>
 hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,
-                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
                           hipStream_t st) {
-    if (tile != 0) return launch_pass19a_sweep<T, TW>(g, in, out, w, div, c, rk, s, tile, st);
+    if (tile != 0)
+        return launch_pass19a_sweep<T, TW>(g, in, out, w, div, c, rk, s, tile, zchunk, st);
     const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)g.nz);
     switch (s) {
     case 1:
@@ -249,7 +250,7 @@ hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<
 // loader options do not apply to this one-field sweep).
 template <typename T, typename TW>
 hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
-                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                          const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
                           hipStream_t st) {
     const TW cgd = TW((double)rk.dt * c.nu3);
     return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
@@ -260,7 +261,8 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
             hipLaunchKernelGGL((pass19b_kernel<T, TW>), grid, dim3(256), 0, st, g, div, out, w, c,
                                rk, cgd);
         } else {
-            const SweepGrid sg = sweep_grid(g, k.tx, k.ty);
+            const int res = resident_blocks<substep19_pass2<T, TW, k.tx, k.ty, 2>>(k.tx * k.ty);
+            const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
             const dim3 grid(sg.blocks), block(k.tx * k.ty);
             const int rm = xcd_remap();
             switch (s) {
@@ -285,10 +287,10 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
 #define FD6_INST19(T, TW)                                                                       \
     template hipError_t launch_pass19a<T, TW>(const Geom&, Fields4<T>, Fields4<T>, Fields4<TW>, \
                                               T*, const Coef<T>&, const RKCoef<TW>&, int, int, \
-                                              hipStream_t);                                    \
+                                              int, hipStream_t);                               \
     template hipError_t launch_pass19b<T, TW>(const Geom&, const T*, Fields4<T>, Fields4<TW>,   \
                                               const Coef<T>&, const RKCoef<TW>&, int, int,     \
-                                              hipStream_t);
+                                              int, hipStream_t);
 FD6_INST19(double, double)
 FD6_INST19(float, float)
 FD6_INST19(float, double)

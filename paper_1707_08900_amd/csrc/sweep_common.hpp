@@ -152,22 +152,50 @@ struct SweepGrid {
     int ntx, nty, zlen, blocks;
 };
 
-inline SweepGrid sweep_grid(const Geom& g, int tx, int ty) {
+// zchunk > 0 fixes the chunk length (planes); 0 chooses it.  resident: how
+// many workgroups of the kernel the device holds at once.  The automatic
+// choice minimises (rounds of resident workgroups) x (planes swept per chunk,
+// including the 6 re-read planes), i.e. it prefers long chunks unless they
+// leave compute units idle.
+inline SweepGrid sweep_grid(const Geom& g, int tx, int ty, int zchunk, int resident) {
     SweepGrid s;
     s.ntx = (g.nx + tx - 1) / tx;
     s.nty = (g.ny + ty - 1) / ty;
     const long long tiles = (long long)s.ntx * s.nty;
-    // enough workgroups to fill 256 CUs several times over; z chunks cost 6
-    // extra planes of loads each, so keep them at least 16 planes long
-    const long long want = 2048;
-    int nch = (int)((want + tiles - 1) / tiles);
-    const int maxch = (g.nz + 15) / 16;
-    if (nch > maxch) nch = maxch;
-    if (nch < 1) nch = 1;
+    int nch = 1;
+    if (zchunk > 0) {
+        nch = (g.nz + zchunk - 1) / zchunk;
+    } else {
+        const long long res = resident > 0 ? resident : 1;
+        long long best = -1;
+        for (int c = 1; c <= (g.nz + 7) / 8; ++c) {
+            const long long len = (g.nz + c - 1) / c;
+            const long long cost = ((tiles * c + res - 1) / res) * (len + 2 * kR);
+            if (best < 0 || cost < best) best = cost, nch = c;
+        }
+    }
     s.zlen = (g.nz + nch - 1) / nch;
     nch = (g.nz + s.zlen - 1) / s.zlen;
     s.blocks = (int)(tiles * nch);
     return s;
+}
+
+// Workgroups of Kernel (block threads) the current device holds at once
+// (the per-CU occupancy is queried once per kernel).
+template <auto Kernel>
+int resident_blocks(int block) {
+    static const int per_cu = [&] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, Kernel, block, 0) != hipSuccess)
+            n = 1;
+        return n > 0 ? n : 1;
+    }();
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    return per_cu * cus;
 }
 
 struct TileXY {

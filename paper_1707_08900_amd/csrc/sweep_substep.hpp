@@ -618,7 +618,7 @@ struct KDirect {
 
 template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
-                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
                             hipStream_t st) {
     return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
         constexpr TileCfg k = kTiles[decltype(I)::value];
@@ -628,7 +628,9 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
             return launch_s<KDirect<T, TW>::template at>(s, grid, dim3(256), st, g, in, out, w,
                                                          c, rk);
         } else {
-            const SweepGrid sg = sweep_grid(g, k.tx, k.ty);
+            const int res =
+                resident_blocks<K55<T, TW, k.tx, k.ty, k.pd, k.ld>::template at<2>::fn>(k.tx * k.ty);
+            const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
             return launch_s<K55<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
                 s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in, out, w, c, rk, sg.ntx, sg.nty,
                 sg.zlen, xcd_remap());
@@ -640,13 +642,15 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
 template <typename T, typename TW>
 hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                                 T* dv, const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
-                                hipStream_t st) {
+                                int zchunk, hipStream_t st) {
     return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
         constexpr TileCfg k = kTiles[decltype(I)::value];
         if constexpr (k.tx == 0) {
             return hipErrorInvalidValue;
         } else {
-            const SweepGrid sg = sweep_grid(g, k.tx, k.ty);
+            const int res =
+                resident_blocks<K19<T, TW, k.tx, k.ty, k.pd, k.ld>::template at<2>::fn>(k.tx * k.ty);
+            const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
             return launch_s<K19<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
                 s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in, out, w, dv, c, rk, sg.ntx,
                 sg.nty, sg.zlen, xcd_remap());

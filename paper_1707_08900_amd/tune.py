@@ -1,7 +1,8 @@
 """Autotuner for the substep kernel shape (55-point and 19-point methods).
 
 Times every kernel shape the library offers (fd6_tile_count) on the caller's
-own box with HIP events, keeps the fastest, and caches the choice in a JSON
+own box with HIP events, then a few z-chunk lengths for the fastest shape,
+keeps the fastest pair, and caches the choice in a JSON
 file keyed by grid shape, precision, variant and device name (path from
 FD6_TUNE_CACHE, default ~/.cache/fd6_tune.json).  Tuning runs real steps, so
 it advances the box's state: call it before init_fields of the actual run,
@@ -51,18 +52,31 @@ def time_tile(box: Box, tile: int, steps: int = 3) -> float:
 
 
 def tune(box: Box, steps: int = 3, use_cache: bool = True,
-         candidates: Optional[list] = None) -> dict:
-    """Pick the fastest kernel shape for this box; returns {tile, ms, timings}."""
+         candidates: Optional[list] = None, zchunks: Optional[list] = None) -> dict:
+    """Pick the fastest kernel shape, then z-chunk length, for this box;
+    returns {tile, zchunk, ms, timings, zchunk_timings}."""
     key = _key(box)
     cache = _load() if use_cache else {}
-    if use_cache and key in cache:
+    if use_cache and key in cache and "zchunk" in cache[key]:
         box.set_tile(cache[key]["tile"])
+        box.set_zchunk(cache[key]["zchunk"])
         return cache[key]
+    box.set_zchunk(0)
     tiles = candidates if candidates is not None else list(range(1, tile_count()))
     timings = {t: time_tile(box, t, steps) for t in tiles}
     best = min(timings, key=timings.get)
     box.set_tile(best)
-    result = {"tile": best, "ms": timings[best], "timings": {str(k): v for k, v in timings.items()}}
+    nz = box.shape[0]
+    zcs = zchunks if zchunks is not None else sorted({z for z in (64, 128, 256) if z < nz} | {nz})
+    ztimes = {0: timings[best]}
+    for z in zcs:
+        box.set_zchunk(z)
+        ztimes[z] = time_tile(box, best, steps)
+    zbest = min(ztimes, key=ztimes.get)
+    box.set_zchunk(zbest)
+    result = {"tile": best, "zchunk": zbest, "ms": ztimes[zbest],
+              "timings": {str(k): v for k, v in timings.items()},
+              "zchunk_timings": {str(k): v for k, v in ztimes.items()}}
     if use_cache:
         cache[key] = result
         path = _cache_path()

@@ -142,6 +142,26 @@ def test_sweep_tiles_are_bitwise_identical(fd6):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("variant", ["55p", "19p"])
+def test_zchunk_does_not_change_results(fd6, variant):
+    """Chunk boundaries in z (1-plane chunks, ragged chunks, whole columns)
+    leave every result bit unchanged."""
+    w = si.noise_box((20, 21, 70), seed=19)
+    outs = []
+    for zc in (0, 1, 7, 16, 1000):
+        box = fd6.Box(w.shape, "fp32", variant)
+        box.set_tile(2)
+        box.set_zchunk(zc)
+        box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+        box.init_fields(w.fields)
+        box.step(2)
+        outs.append(box.get_fields())
+        box.close()
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
 def test_runs_are_deterministic(fd6):
     w = si.noise_box((16, 24, 40), seed=9)
     a = run_gpu(fd6, w, "fp32", nsteps=3)
