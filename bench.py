@@ -70,7 +70,7 @@ def make_box(fd6, w, dev_fields, precision, variant, tune=True):
     if tune:
         from paper_1707_08900_amd import tune as tuner
         box.init_fields(dev_fields)
-        tuned = tuner.tune(box, steps=2, use_cache=False)
+        tuned = tuner.tune(box, steps=2, use_cache=False, reduce=True)
     box.init_fields(dev_fields)
     return box, tuned
 

@@ -261,6 +261,13 @@ hipError_t launch_reduce(const Geom& g, Fields4<T> f, double* partials, double* 
     return hipGetLastError();
 }
 
+hipError_t launch_reduce_final(const double* partials, int nparts, double* result, double dV,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, nparts,
+                       result, dV);
+    return hipGetLastError();
+}
+
 #define FD6_INST_T(T)                                                                        \
     template hipError_t launch_ghost_fill<T>(const Geom&, Fields4<T>, int, hipStream_t);    \
     template hipError_t launch_import<T>(const Geom&, const double*, T*, long long, int,    \

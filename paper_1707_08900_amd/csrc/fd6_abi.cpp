@@ -172,7 +172,7 @@ int make_plan(const fd6_desc* d, Plan* p) {
     p->off_div = off;
     if (d->variant == FD6_19P) off += fbytes;
     p->off_partials = off;
-    off += round_up((size_t)kReduceBlocks * kReduceSlots * sizeof(double), kAlign);
+    off += round_up((size_t)kFusedPartials * kReduceSlots * sizeof(double), kAlign);
     p->off_result = off;
     off += kAlign;
     const long long plane_c = (long long)d->nx * d->ny;
@@ -303,10 +303,12 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
         if (rc) return rc;
         b->ghosts_ok[b->cur] = true;
     }
+    int nparts = 0;  // > 0: substep 3 wrote the diagnostics partials itself
     if (b->desc.variant == FD6_55P) {
+        double* parts = (red_out && s == 3) ? b->partials : nullptr;
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->zchunk,
-                                               b->stream)));
+            HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->zchunk, parts,
+                                               kFusedPartials, &nparts, b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;
@@ -337,8 +339,11 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
     b->cur ^= 1;
     if (red_out && s == 3) {
         const double dV = b->params.dx * b->params.dy * b->params.dz;
-        HIPCHK(b, launch_reduce<T>(g, fields_of<T>(b->state[b->cur]), b->partials, red_out, dV,
-                                   b->stream));
+        if (nparts > 0)
+            HIPCHK(b, launch_reduce_final(b->partials, nparts, red_out, dV, b->stream));
+        else
+            HIPCHK(b, launch_reduce<T>(g, fields_of<T>(b->state[b->cur]), b->partials, red_out,
+                                       dV, b->stream));
     }
     return FD6_OK;
 }

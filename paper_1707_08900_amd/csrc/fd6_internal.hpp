@@ -95,10 +95,14 @@ hipError_t launch_zero_w(const Geom& g, Fields4<TW> w, hipStream_t s);
 
 // 55-point fused right-hand side + RK3 update for substep s (1, 2, 3) with
 // kernel shape `tile` and z-chunk length `zchunk` (0: chosen by the launcher).
+// With partials != nullptr, substep 3 of a z-sweep shape whose grid has at
+// most part_cap workgroups also writes one FP64 diagnostics partial per
+// workgroup (kReduceSlots doubles each) and sets *nparts to their number;
+// otherwise *nparts = 0 and the caller reduces separately.
 template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                             const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                            hipStream_t st);
+                            double* partials, int part_cap, int* nparts, hipStream_t st);
 // Whether a kernel shape reads the ghost zone of its input (the z-sweep
 // shapes resolve the periodic images in their loader instead).
 bool substep55_reads_ghosts(int tile);
@@ -144,10 +148,14 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
 
 // FP64 reductions: per-block partials then one fixed-order final block.
 constexpr int kReduceBlocks = 1024;
+constexpr int kFusedPartials = 8192;  // partial slots for diagnostics fused into substep 3
 constexpr int kReduceSlots = 8;  // mass, ke, sum lnrho, umax, nonfinite, pad
 template <typename T>
 hipError_t launch_reduce(const Geom& g, Fields4<T> f, double* partials, double* result,
                          double dV, hipStream_t s);
+// Final fixed-order combination of nparts partials into result.
+hipError_t launch_reduce_final(const double* partials, int nparts, double* result, double dV,
+                               hipStream_t s);
 
 
 int substep55_tile_count();

@@ -155,6 +155,8 @@ struct SweepRegs {
     T pf[2][4];      // prefetched interior values of the next plane(s)
     T ph[2][NH][4];  // prefetched halo values of the next plane(s)
     TW wq[2][4];     // RK3 register of the output point (PD = 2: loaded a step early)
+    double red[5];   // fused diagnostics of the thread's column (RED): sum rho,
+                     // sum rho u^2 / 2, sum lnrho, max u^2, non-finite count
 };
 
 // Memory operations of a plane step are never skipped by a branch: a step
@@ -213,8 +215,8 @@ __device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
     }
 }
 
-template <int PH, int S, int PD, bool LD, bool P19, typename T, typename TW, int TX, int TY,
-          int NH>
+template <int PH, int S, int PD, bool LD, bool P19, bool RED, typename T, typename TW, int TX,
+          int TY, int NH>
 __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, TW, NH>& R,
                                            const SweepCtx<T, TX, TY, LD>& X, T* lds,
                                            lds_t<T> lds3, const Geom& g, const Fields4<T>& in,
@@ -337,10 +339,12 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         assemble_rhs(u, gr, J, Lf, cf.nu, cf.cs2, r);
         // ghost corner (-3, -3) of output plane o
         const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
+        T vout[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             TW wv = S == 1 ? TW(0) : R.wq[WS][f];
             const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv, rk);
+            vout[f] = v;
             bstore(v, plane_rsrc(out.f[f] + ocorner, ob), X.lane_o);
             if constexpr (S != 3)
                 bstore(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, wb), X.lane_w);
@@ -348,6 +352,20 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         // 19-point pass 1 also stores the divergence for pass 2
         if constexpr (P19)
             bstore(J[0][0] + J[1][1] + J[2][2], plane_rsrc(dv + ocorner, ob), X.lane_o);
+        // FP64 diagnostics of the new state, from the values just stored (the
+        // same per-point quantities as the standalone reduction)
+        if constexpr (RED) {
+            const bool valid = outstep && X.lane_o != kDropOffset;
+            const double lr = vout[0], ux = vout[1], uy = vout[2], uz = vout[3];
+            const double rho = exp(lr);
+            const double u2 = ux * ux + uy * uy + uz * uz;
+            const bool finite = isfinite(lr) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+            R.red[0] += valid ? rho : 0.0;
+            R.red[1] += valid ? 0.5 * rho * u2 : 0.0;
+            R.red[2] += valid ? lr : 0.0;
+            R.red[3] = (valid && u2 > R.red[3]) ? u2 : R.red[3];
+            R.red[4] += (valid && !finite) ? 1.0 : 0.0;
+        }
     }
 
     // (C) the rest of plane p for this column: x / y first derivatives of the
@@ -472,11 +490,50 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
 // One tile-chunk: columns [x0, x0 + TX) x [y0, y0 + TY) of the box, output
 // planes [zb, ze).  Every thread of the workgroup calls it with the same
 // arguments.  P19: pass 1 of the 19-point method (dv receives the divergence).
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool P19 = false>
+// Combines the per-thread diagnostics of a workgroup in a fixed order (xor
+// tree within each wave, then waves in order) and stores the partial:
+// sums for slots 0-2 and 4, the maximum for slot 3.
+template <int NW>
+__device__ __forceinline__ void red_store_n(double v[5], double* part) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double o = __shfl_xor(v[i], off, 64);
+            v[i] = i == 3 ? (o > v[i] ? o : v[i]) : v[i] + o;
+        }
+    }
+    __shared__ double sw[NW][5];
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) sw[wv][i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < NW; ++k)
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                a[i] = i == 3 ? (sw[k][i] > a[i] ? sw[k][i] : a[i]) : a[i] + sw[k][i];
+        double* p = part + (size_t)blockIdx.x * kReduceSlots;
+        p[0] = a[0];
+        p[1] = a[1];
+        p[2] = a[2];
+        p[3] = sqrt(a[3]);  // max |u| = sqrt(max |u|^2): sqrt is monotonic
+        p[4] = a[4];
+    }
+}
+
+// RED: also reduce the FP64 diagnostics of the output and store this
+// workgroup's partial at part[blockIdx.x * kReduceSlots ...].
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool P19 = false,
+          bool RED = false>
 __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
                                            const Coef<T>& cf, const RKCoef<TW>& rk, int x0,
-                                           int y0, int zb, int ze, T* lds, lds_t<T> lds3) {
+                                           int y0, int zb, int ze, T* lds, lds_t<T> lds3,
+                                           double* part = nullptr) {
     using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int NH = Sh::NH;
     SweepCtx<T, TX, TY, LD> X;
@@ -494,6 +551,8 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int s = 0; s < 8; ++s) R.L[i][s] = T(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) R.red[i] = 0.0;
 
     const int nplanes = (ze - zb) + 2 * kR;
     if constexpr (LD) {
@@ -504,15 +563,24 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
             sweep_prefetch<1>(R, X, in, plane_corner(g, zb - kR + 1), X.plane_bytes);
     }
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        sweep_step<0, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
-        sweep_step<1, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
-        sweep_step<2, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
-        sweep_step<3, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
-        sweep_step<4, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
-        sweep_step<5, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
-        sweep_step<6, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
-        sweep_step<7, S, PD, LD, P19>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk);
+        sweep_step<0, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
+        sweep_step<1, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
+        sweep_step<2, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
+        sweep_step<3, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
+        sweep_step<4, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
+        sweep_step<5, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
+        sweep_step<6, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
+        sweep_step<7, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
+                                             rk);
     }
+    if constexpr (RED) red_store_n<SweepShape<T, TX, TY, LD>::NW>(R.red, part);
 }
 
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD>
@@ -525,6 +593,19 @@ void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<
     if (t.zb >= t.ze) return;
     sweep_tile<T, TW, TX, TY, S, PD, LD>(g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds,
                                      (lds_t<T>)lds);
+}
+
+// Substep 3 with the FP64 diagnostics of the new state fused in: one partial
+// per workgroup (every workgroup of the grid has a non-empty chunk).
+template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+__global__ __launch_bounds__(TX* TY)
+void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
+                         RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, double* part) {
+    using Sh = SweepShape<T, TX, TY, LD>;
+    __shared__ T lds[2 * 4 * Sh::FS];
+    const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    sweep_tile<T, TW, TX, TY, 3, PD, LD, false, true>(g, in, out, w, nullptr, cf, rk, t.tx, t.ty,
+                                                     t.zb, t.ze, lds, (lds_t<T>)lds, part);
 }
 
 // Pass 1 of the 19-point method (Sec. 4.2, Algorithm 3): the same sweep
@@ -619,7 +700,8 @@ struct KDirect {
 template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                             const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                            hipStream_t st) {
+                            double* partials, int part_cap, int* nparts, hipStream_t st) {
+    if (nparts) *nparts = 0;
     return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
         constexpr TileCfg k = kTiles[decltype(I)::value];
         if constexpr (k.tx == 0) {
@@ -631,6 +713,26 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
             const int res =
                 resident_blocks<K55<T, TW, k.tx, k.ty, k.pd, k.ld>::template at<2>::fn>(k.tx * k.ty);
             const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
+            // fuse only where the extra accumulators cost no occupancy
+            static const bool fuse_ok = [] {
+                int a = 0, b = 0;
+                const int blk = k.tx * k.ty;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &a, substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld>, blk, 0) !=
+                        hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &b, substep55_sweep<T, TW, k.tx, k.ty, 3, k.pd, k.ld>, blk, 0) !=
+                        hipSuccess)
+                    return false;
+                return a >= b && a > 0;
+            }();
+            if (s == 3 && partials && nparts && fuse_ok && sg.blocks <= part_cap) {
+                hipLaunchKernelGGL((substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld>),
+                                   dim3(sg.blocks), dim3(k.tx * k.ty), 0, st, g, in, out, w, c,
+                                   rk, sg.ntx, sg.nty, sg.zlen, xcd_remap(), partials);
+                *nparts = sg.blocks;
+                return hipGetLastError();
+            }
             return launch_s<K55<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
                 s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in, out, w, c, rk, sg.ntx, sg.nty,
                 sg.zlen, xcd_remap());

@@ -38,24 +38,35 @@ def _load() -> Dict[str, dict]:
         return {}
 
 
-def time_tile(box: Box, tile: int, steps: int = 3) -> float:
-    """Milliseconds per full RK3 step with the given kernel shape."""
+def time_tile(box: Box, tile: int, steps: int = 3, reduce: bool = False) -> float:
+    """Milliseconds per full RK3 step with the given kernel shape (reduce:
+    steps that also produce the FP64 diagnostics, as step_reduce does)."""
     box.set_tile(tile)
-    box.step(1)  # warm-up (code object load, caches)
+    red = torch.zeros(8, dtype=torch.float64, device=box.device) if reduce else None
+
+    def run(n):
+        for _ in range(n):
+            if reduce:
+                box.step_reduce(1, red)
+            else:
+                box.step(1)
+
+    run(1)  # warm-up (code object load, caches)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(box.stream)
-    box.step(steps)
+    run(steps)
     e1.record(box.stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / steps
 
 
 def tune(box: Box, steps: int = 3, use_cache: bool = True,
-         candidates: Optional[list] = None, zchunks: Optional[list] = None) -> dict:
+         candidates: Optional[list] = None, zchunks: Optional[list] = None,
+         reduce: bool = False) -> dict:
     """Pick the fastest kernel shape, then z-chunk length, for this box;
     returns {tile, zchunk, ms, timings, zchunk_timings}."""
-    key = _key(box)
+    key = _key(box) + ("|reduce" if reduce else "")
     cache = _load() if use_cache else {}
     if use_cache and key in cache and "zchunk" in cache[key]:
         box.set_tile(cache[key]["tile"])
@@ -63,7 +74,7 @@ def tune(box: Box, steps: int = 3, use_cache: bool = True,
         return cache[key]
     box.set_zchunk(0)
     tiles = candidates if candidates is not None else list(range(1, tile_count()))
-    timings = {t: time_tile(box, t, steps) for t in tiles}
+    timings = {t: time_tile(box, t, steps, reduce) for t in tiles}
     best = min(timings, key=timings.get)
     box.set_tile(best)
     nz = box.shape[0]
@@ -71,7 +82,7 @@ def tune(box: Box, steps: int = 3, use_cache: bool = True,
     ztimes = {0: timings[best]}
     for z in zcs:
         box.set_zchunk(z)
-        ztimes[z] = time_tile(box, best, steps)
+        ztimes[z] = time_tile(box, best, steps, reduce)
     zbest = min(ztimes, key=ztimes.get)
     box.set_zchunk(zbest)
     result = {"tile": best, "zchunk": zbest, "ms": ztimes[zbest],
