@@ -35,7 +35,7 @@ ALG_BYTES = {("55p", "fp32"): 160, ("55p", "fp64"): 320, ("55p", "fp32_acc64"): 
              ("19p", "fp32"): 304, ("19p", "fp64"): 608}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_substep55_fp32_512.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1707_08900_amd", "csrc", f)
-               for f in ("sweep_common.hpp", "substep55_impl.hpp", "substep55_f32.hip")]
+               for f in ("sweep_common.hpp", "sweep_substep.hpp", "substep55_f32.hip")]
 
 
 def log(msg):
@@ -50,15 +50,18 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def load_traffic():
+def load_traffic(shape):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
+    taken on the current kernel source with the same kernel shape and
+    z-chunk length."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_source_sha") != source_sha(KERNEL_SRCS):
+        return None
+    if (t.get("tile"), t.get("zchunk")) != (shape.get("tile"), shape.get("zchunk")):
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -196,6 +199,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration for rocprofv3)")
     ap.add_argument("--tile", type=int, default=None,
                     help="kernel shape of the headline run (skips the autotuner)")
+    ap.add_argument("--zchunk", type=int, default=0,
+                    help="z-chunk length with --tile (0: automatic)")
     a = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -235,7 +240,8 @@ def main():
     box, tuned = make_box(fd6, w, dev_fields, "fp32", "55p", tune=a.tile is None)
     if a.tile is not None:
         box.set_tile(a.tile)
-        tuned = {"tile": a.tile}
+        box.set_zchunk(a.zchunk)
+        tuned = {"tile": a.tile, "zchunk": a.zchunk}
     log(f"kernel shape: {tuned}")
     wall, ev_ms, (kms, klaunch, gms, glaunch) = timed_steps(torch, box, red, a.steps, a.warmup)
     r = red.cpu().numpy()
@@ -249,7 +255,7 @@ def main():
     alg_per_launch = n ** 3 * ALG_BYTES[("55p", "fp32")] / 3.0
     avg_launch_s = kms * 1e-3 / klaunch
     achieved = alg_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic()
+    traffic = load_traffic(tuned)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,

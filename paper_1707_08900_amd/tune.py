@@ -79,7 +79,7 @@ def tune(box: Box, steps: int = 3, use_cache: bool = True,
     box.set_tile(best)
     nz = box.shape[0]
     zcs = zchunks if zchunks is not None else sorted({z for z in (64, 128, 256) if z < nz} | {nz})
-    ztimes = {0: timings[best]}
+    ztimes = {}  # explicit lengths only, so the choice is reproducible
     for z in zcs:
         box.set_zchunk(z)
         ztimes[z] = time_tile(box, best, steps, reduce)
