@@ -245,6 +245,11 @@ def main():
     log(f"kernel shape: {tuned}")
     wall, ev_ms, (kms, klaunch, gms, glaunch) = timed_steps(torch, box, red, a.steps, a.warmup)
     r = red.cpu().numpy()
+    # the same steps replayed from a captured graph per step (no per-launch
+    # events in this mode)
+    box.set_graph(True)
+    _, gev_ms, _ = timed_steps(torch, box, red, a.steps, 2, timing=False)
+    box.set_graph(False)
     box.close()
     ms_per_step = ev_ms / a.steps
     value = n ** 3 * a.steps / (ev_ms * 1e-3)
@@ -270,6 +275,9 @@ def main():
     step_alg = ALG_BYTES[("55p", "fp32")]
     forms["fp32"] = {"updates_per_s": value, "ms_per_step": ms_per_step,
                      "hbm_frac_step": value * step_alg / (HBM_PEAK_GBS * 1e9)}
+    forms["fp32_graph"] = {"updates_per_s": n ** 3 * a.steps / (gev_ms * 1e-3),
+                           "ms_per_step": gev_ms / a.steps}
+    log(f"fp32 55p {n}^3 graph replay: {gev_ms / a.steps:.3f} ms/step")
     if not a.no_check:
         forms["fp32"]["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields, "fp32", "55p")
     if not a.no_forms:

@@ -175,6 +175,17 @@ int fd6_set_tile(fd6_box *box, int32_t tile);
  * do not depend on it (bit for bit).  FD6_EINVAL if zchunk < 0. */
 int fd6_set_zchunk(fd6_box *box, int32_t zchunk);
 
+/* Graph mode (Algorithm 2 as one HIP graph per step): with enable != 0,
+ * fd6_rk3_step and fd6_rk3_step_reduce capture one full step (three substeps,
+ * and for the reducing variant the diagnostics of the last step, with d_out
+ * recorded) per starting state set on a private stream the first time they
+ * need it, and then replay it on the box's stream.  Results are bit for bit
+ * those of the launch-by-launch path.  Captured steps are dropped by
+ * fd6_set_params, fd6_set_tile, fd6_set_zchunk and disabling; a different
+ * d_out re-captures the reducing step.  Event timing (fd6_set_timing)
+ * bypasses graphs.  Default: off. */
+int fd6_set_graph(fd6_box *box, int32_t enable);
+
 /* Kernel timing with HIP events recorded on the box's stream around every
  * launch of the main substep kernel(s) (55-point fused kernel; both passes of
  * the 19-point method) and of the ghost fill.  enable != 0 starts (and

@@ -29,7 +29,8 @@ ABI_SYMBOLS = (
     "fd6_abi_version", "fd6_status_string", "fd6_workspace_bytes", "fd6_create", "fd6_destroy",
     "fd6_set_stream", "fd6_set_params", "fd6_init_fields", "fd6_init_fields_device",
     "fd6_rk3_step", "fd6_rk3_step_reduce", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
-    "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_zchunk", "fd6_set_timing",
+    "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_zchunk", "fd6_set_graph",
+    "fd6_set_timing",
     "fd6_get_timing",
     "fd6_last_error", "fd6_batch_workspace_bytes", "fd6_batch_create", "fd6_batch_destroy",
     "fd6_batch_set_params", "fd6_batch_init_fields", "fd6_batch_set_schedule",
@@ -88,6 +89,7 @@ def _declare(lib):
         "fd6_tile_count": (I, []),
         "fd6_set_tile": (I, [P, ctypes.c_int32]),
         "fd6_set_zchunk": (I, [P, ctypes.c_int32]),
+        "fd6_set_graph": (I, [P, ctypes.c_int32]),
         "fd6_last_error": (ctypes.c_char_p, [P]),
         "fd6_batch_workspace_bytes": (I, [ctypes.c_int32, ctypes.POINTER(Fd6Desc),
                                           ctypes.POINTER(ctypes.c_size_t)]),
@@ -266,6 +268,10 @@ class Box:
     def set_zchunk(self, zchunk: int):
         """z-chunk length of the sweep kernels (0: automatic)."""
         self._check(self.lib.fd6_set_zchunk(self.h, int(zchunk)), "fd6_set_zchunk")
+
+    def set_graph(self, enable: bool):
+        """Replay each step as a captured HIP graph."""
+        self._check(self.lib.fd6_set_graph(self.h, 1 if enable else 0), "fd6_set_graph")
 
 
 class Batch:

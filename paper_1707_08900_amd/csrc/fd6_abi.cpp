@@ -50,7 +50,24 @@ struct fd6_box {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_kernel, ev_ghost;
     std::vector<hipEvent_t> ev_pool;
+    // optional captured graphs of one full step, per starting parity; the
+    // reducing variant also records its diagnostics target
+    bool use_graph = false;
+    hipStream_t cap = nullptr;  // private stream used only for graph capture
+    hipGraphExec_t gstep[2] = {nullptr, nullptr};
+    hipGraphExec_t gred[2] = {nullptr, nullptr};
+    double* gred_out[2] = {nullptr, nullptr};
+    void drop_graphs() {
+        for (int i = 0; i < 2; ++i) {
+            if (gstep[i]) (void)hipGraphExecDestroy(gstep[i]);
+            if (gred[i]) (void)hipGraphExecDestroy(gred[i]);
+            gstep[i] = gred[i] = nullptr;
+            gred_out[i] = nullptr;
+        }
+    }
     ~fd6_box() {
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
         for (auto& p : ev_kernel) ev_pool.push_back(p.first), ev_pool.push_back(p.second);
         for (auto& p : ev_ghost) ev_pool.push_back(p.first), ev_pool.push_back(p.second);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -348,15 +365,75 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
     return FD6_OK;
 }
 
+// One full step (Algorithm 2: three substeps); red_out != nullptr also
+// produces the diagnostics of the new state.
+template <typename T, typename TW>
+int one_step(fd6_box* b, double* red_out) {
+    const double dt = b->params.dt;
+    for (int s = 0; s < 3; ++s) {
+        RKCoef<TW> rk{TW(kAlpha[s]), TW(kBeta[s]), TW(dt)};
+        int rc = do_substep<T, TW>(b, s + 1, rk, red_out);
+        if (rc) return rc;
+    }
+    return FD6_OK;
+}
+
+// Captures one full step starting from state set `parity` into *out.  The
+// capture runs on a private stream; a kernel shape that reads ghost zones
+// records a ghost pass in every substep (the lazy bookkeeping cannot follow
+// replays).  The box's stream, parity and ghost flags are restored.
+template <typename T, typename TW>
+int capture_step(fd6_box* b, int parity, double* red_out, hipGraphExec_t* out) {
+    if (!b->cap) HIPCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    hipStream_t user = b->stream;
+    const int cur = b->cur;
+    b->stream = b->cap;
+    b->cur = parity;
+    b->ghosts_ok[0] = b->ghosts_ok[1] = false;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? one_step<T, TW>(b, red_out) : FD6_OK;
+    hipGraph_t g = nullptr;
+    hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(b->cap, &g) : e;
+    b->stream = user;
+    b->cur = cur;
+    b->ghosts_ok[0] = b->ghosts_ok[1] = false;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e2 != hipSuccess) return hip_fail(b, e2, "graph capture of one step");
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(b, e, "hipGraphInstantiate");
+    return FD6_OK;
+}
+
 template <typename T, typename TW>
 int do_steps(fd6_box* b, int nsteps, double* red_out = nullptr) {
-    const double dt = b->params.dt;
-    for (int n = 0; n < nsteps; ++n)
-        for (int s = 0; s < 3; ++s) {
-            RKCoef<TW> rk{TW(kAlpha[s]), TW(kBeta[s]), TW(dt)};
-            int rc = do_substep<T, TW>(b, s + 1, rk, n == nsteps - 1 ? red_out : nullptr);
+    if (!b->use_graph || b->timing) {
+        for (int n = 0; n < nsteps; ++n) {
+            int rc = one_step<T, TW>(b, n == nsteps - 1 ? red_out : nullptr);
             if (rc) return rc;
         }
+        return FD6_OK;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        const bool red = red_out && n == nsteps - 1;
+        const int p = b->cur;
+        hipGraphExec_t* x = red ? &b->gred[p] : &b->gstep[p];
+        if (red && *x && b->gred_out[p] != red_out) {
+            (void)hipGraphExecDestroy(*x);
+            *x = nullptr;
+        }
+        if (!*x) {
+            int rc = capture_step<T, TW>(b, p, red ? red_out : nullptr, x);
+            if (rc) return rc;
+            if (red) b->gred_out[p] = red_out;
+        }
+        HIPCHK(b, hipGraphLaunch(*x, b->stream));
+        b->cur ^= 1;  // three in/out swaps
+        b->ghosts_ok[0] = b->ghosts_ok[1] = false;
+    }
     return FD6_OK;
 }
 
@@ -821,6 +898,7 @@ int fd6_set_params(fd6_box* b, const fd6_params* p) {
         return FD6_EINVAL;
     b->params = *p;
     b->have_params = true;
+    b->drop_graphs();  // coefficients are baked into captured steps
     return FD6_OK;
 }
 
@@ -986,7 +1064,15 @@ const char* fd6_last_error(const fd6_box* b) { return b ? b->err.c_str() : ""; }
 // one-thread-per-point kernel, 1.. = z-sweep tile shapes).
 int fd6_set_tile(fd6_box* b, int32_t tile) {
     if (!b || tile < 0 || tile >= substep55_tile_count()) return FD6_EINVAL;
+    if (tile != b->tile) b->drop_graphs();
     b->tile = tile;
+    return FD6_OK;
+}
+
+int fd6_set_graph(fd6_box* b, int32_t enable) {
+    if (!b) return FD6_EINVAL;
+    b->use_graph = enable != 0;
+    if (!b->use_graph) b->drop_graphs();
     return FD6_OK;
 }
 
@@ -994,6 +1080,7 @@ int fd6_tile_count(void) { return substep55_tile_count(); }
 
 int fd6_set_zchunk(fd6_box* b, int32_t zchunk) {
     if (!b || zchunk < 0) return FD6_EINVAL;
+    if (zchunk != b->zchunk) b->drop_graphs();
     b->zchunk = zchunk;
     return FD6_OK;
 }

@@ -109,6 +109,8 @@ def test_create_validation_and_state_machine(pkg):
         assert lib.fd6_set_tile(h, n) == -1
         assert lib.fd6_set_tile(h, -1) == -1
         assert lib.fd6_set_tile(h, 0) == 0
+        assert lib.fd6_set_graph(h, 1) == 0 and lib.fd6_set_graph(h, 0) == 0
+        assert lib.fd6_set_graph(None, 1) == -1
         assert lib.fd6_set_zchunk(h, -1) == -1
         assert lib.fd6_set_zchunk(h, 0) == 0 and lib.fd6_set_zchunk(h, 10 ** 6) == 0
         assert lib.fd6_last_error(h) == b""

@@ -162,6 +162,43 @@ def test_zchunk_does_not_change_results(fd6, variant):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("variant,tile", [("55p", 6), ("55p", 0), ("19p", 6), ("19p", 0)])
+def test_graph_mode_matches_eager(fd6, variant, tile):
+    """Captured steps replayed several times, with eager work (exports,
+    reductions) between the replays, equal the launch-by-launch path bit for
+    bit; so do the reducing step (re-captured for a new target) and a
+    re-capture after new parameters."""
+    import torch
+    w = si.noise_box((20, 21, 22), seed=23)
+
+    def make(graph):
+        box = fd6.Box(w.shape, "fp64", variant)
+        box.set_tile(tile)
+        box.set_graph(graph)
+        box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+        box.init_fields(w.fields)
+        return box
+
+    eager, graph = make(False), make(True)
+    for rnd in range(3):
+        eager.step(2)
+        graph.step(2)
+        for a, b in zip(eager.get_fields(), graph.get_fields()):
+            assert np.array_equal(a, b), rnd
+        assert eager.reduce() == graph.reduce()
+    for rnd in range(2):
+        r1 = torch.zeros(8, dtype=torch.float64, device="cuda")
+        r2 = torch.zeros(8, dtype=torch.float64, device="cuda")
+        eager.step_reduce(3, r1)
+        graph.step_reduce(3, r2)
+        assert np.array_equal(r1.cpu().numpy(), r2.cpu().numpy()), rnd
+    for box in (eager, graph):
+        box.set_params(2 * w.nu, w.cs, w.dx, w.dy, w.dz, 0.5 * w.dt)
+        box.step(3)
+    for a, b in zip(eager.get_fields(), graph.get_fields()):
+        assert np.array_equal(a, b)
+
+
 def test_runs_are_deterministic(fd6):
     w = si.noise_box((16, 24, 40), seed=9)
     a = run_gpu(fd6, w, "fp32", nsteps=3)
