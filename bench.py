@@ -140,7 +140,7 @@ def batch_form(torch, fd6, si, steps):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     timings = {}
-    for tile in (1, 4, 8):
+    for tile in (1, 4, 6, 8):
         for zc in (0, 32):
             b.set_schedule(tile, zc)
             b.step(1)
@@ -179,10 +179,24 @@ def cpu_baseline(orc, si, w, threads):
     orc.rk3(sample, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, threads)
     dt = time.perf_counter() - t0
     pts = nzs * w.shape[1] * w.shape[2]
+    # the same oracle on one core, on the first 16 of those planes
+    nz1 = min(16, nzs)
+    s1 = [f[:nz1].copy() for f in w.fields]
+    t0 = time.perf_counter()
+    orc.rk3(s1, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, 1)
+    dt1 = time.perf_counter() - t0
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": pts / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "value_1core": nz1 * w.shape[1] * w.shape[2] / dt1,
             "sample": f"first {nzs} z-planes of the workload as a periodic "
                       f"{w.shape[2]}x{w.shape[1]}x{nzs} box, one RK3 step, FP64 C oracle "
-                      f"with {threads} OpenMP threads ({dt:.2f} s)"}
+                      f"with {threads} OpenMP threads ({dt:.2f} s); value_1core: first {nz1} "
+                      f"planes on 1 thread ({dt1:.2f} s); host CPU: {cpu}"}
 
 
 def main():

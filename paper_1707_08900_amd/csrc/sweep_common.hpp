@@ -216,8 +216,9 @@ __device__ __forceinline__ TileXY sweep_tile_of(const Geom& g, int TX, int TY, i
 
 // Kernel shapes of the z-sweep substeps.  Index 0 is the direct kernel (one
 // thread per point, taps from the ghost zone); the others are (TX, TY) column
-// tiles.  pd: how many planes ahead the register loader fetches (2 also loads
-// the RK3 register one step early); ld: the LDS-copy loader instead.
+// tiles.  pd: how many planes ahead the register loader fetches (1, 2 or 4;
+// 2 and 4 also load the RK3 register one step early); ld: the LDS-copy loader
+// instead.
 struct TileCfg {
     int tx, ty, pd;
     bool ld;
@@ -225,7 +226,7 @@ struct TileCfg {
 constexpr TileCfg kTiles[] = {
     {0, 0, 1, false},   {64, 4, 1, false}, {64, 8, 1, false}, {128, 4, 1, false},
     {32, 8, 1, false},  {64, 4, 2, false}, {64, 8, 2, false}, {128, 4, 2, false},
-    {32, 8, 2, false},  {64, 8, 1, true}};
+    {32, 8, 2, false},  {64, 8, 1, true},  {64, 8, 4, false}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // Calls f(std::integral_constant<int, tile>) so that f can use kTiles[tile]

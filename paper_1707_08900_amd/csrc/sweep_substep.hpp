@@ -152,8 +152,8 @@ struct SweepRegs {
     T q[4][8];       // raw column values of the 4 fields, ring over planes
     T L[3][8];       // pending linear viscous term of the 3 momentum components
     T dd[4][8];      // x/y first derivatives of the 4 fields, ring of 4 planes
-    T pf[2][4];      // prefetched interior values of the next plane(s)
-    T ph[2][NH][4];  // prefetched halo values of the next plane(s)
+    T pf[4][4];      // prefetched interior values of the next plane(s)
+    T ph[4][NH][4];  // prefetched halo values of the next plane(s)
     TW wq[2][4];     // RK3 register of the output point (PD = 2: loaded a step early)
     double red[5];   // fused diagnostics of the thread's column (RED): sum rho,
                      // sum rho u^2 / 2, sum lnrho, max u^2, non-finite count
@@ -232,15 +232,16 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
 
     T* buf = lds + (PH & 1) * 4 * Sh::FS;
     const int ci = (threadIdx.x / TX + kR) * W + (threadIdx.x % TX + kR);
-    // register sets: plane p sits in set RS; the RK3 register of output o in
-    // set WS
-    constexpr int RS = PD == 2 ? (PH & 1) : 0;
-    constexpr int WS = PD == 2 ? (PH & 1) : 0;
+    // register sets: plane p sits in set RS (PD sets, PD divides the unroll
+    // of 8); the RK3 register of output o in set WS
+    static_assert(PD == 1 || PD == 2 || PD == 4, "prefetch depth");
+    constexpr int RS = PH % PD;
+    constexpr int WS = PD >= 2 ? (PH & 1) : 0;
     if constexpr (!LD) {
         // RK3 register of an output point, issued early: PD = 1 loads the one
         // finished in this step, PD = 2 the one finished in the next step
         if constexpr (S != 1) {
-            if constexpr (PD == 2) {
+            if constexpr (PD >= 2) {
                 const bool next_out = t + 1 >= 2 * kR && t + 1 < nplanes;
                 load_w<(PH + 1) & 1>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u, X.lane_w);
             } else {
@@ -559,8 +560,13 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         sweep_dma<T, TX, TY>(X, in, plane_corner(g, zb - kR), lds3, X.plane_bytes);
     } else {
         sweep_prefetch<0>(R, X, in, plane_corner(g, zb - kR), X.plane_bytes);
-        if constexpr (PD == 2)
+        if constexpr (PD >= 2)
             sweep_prefetch<1>(R, X, in, plane_corner(g, zb - kR + 1), X.plane_bytes);
+        if constexpr (PD == 4) {
+            // a chunk sweeps at least 7 planes, so these exist
+            sweep_prefetch<2>(R, X, in, plane_corner(g, zb - kR + 2), X.plane_bytes);
+            sweep_prefetch<3>(R, X, in, plane_corner(g, zb - kR + 3), X.plane_bytes);
+        }
     }
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
         sweep_step<0, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,

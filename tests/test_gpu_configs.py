@@ -5,10 +5,12 @@
 * 512^3 (and 256^3) single box, FP32, |k| <= 16, A = 0.1, nu = 1e-3: one step
   in the benchmark's kernel shape, sampled points against the oracle's local
   patch update (a point after one step depends only on a 19^3 neighbourhood).
-* 768^3 linear sound wave lnrho = 1e-4 sin(4x), u = 0, nu = 1e-4: the
-  x-profile equals the oracle's exact 768 x 8 x 8 slab replica (the field
-  never varies in y and z), every column is identical, and the wave follows
-  the fully discrete 2x2 closed form.
+* 768^3 linear sound wave lnrho = 1e-4 sin(4x), u = 0, nu = 1e-4, 1000 steps:
+  the x-profile equals the oracle's exact 768 x 8 x 8 slab replica (the field
+  never varies in y and z), every column is identical, the wave follows the
+  fully discrete 2x2 closed form, and against the continuum it shows the RK3
+  amplitude loss the closed forms predict; its 64^3 replica against the
+  oracle on the full fields.
 * the 64-box ensemble: every box bitwise equal to its single-box run.
 """
 import math
@@ -109,6 +111,10 @@ def test_large_box_sampled_points(fd6, orc, n):
 
 
 def sound_closed_form(k, h, cs, nu, dt, nsteps, A):
+    """Fully discrete linear 55-point scheme on one mode: the 2x2 system
+    L' = k1 U, U' = -cs^2 k1 L - (4/3) nu k2^2 U (k1, k2^2 the symbols of the
+    sixth-order D1 and D2, Sec. 2.3) advanced by nsteps RK3 steps, whose
+    amplification matrix is the cubic Taylor polynomial of dt M."""
     t = k * h
     k1 = (45 * math.sin(t) - 9 * math.sin(2 * t) + math.sin(3 * t)) / (30 * h)
     k2 = (490 - 540 * math.cos(t) + 54 * math.cos(2 * t) - 4 * math.cos(3 * t)) / (180 * h * h)
@@ -117,42 +123,94 @@ def sound_closed_form(k, h, cs, nu, dt, nsteps, A):
     return np.linalg.matrix_power(P, nsteps) @ np.array([A, 0.0])
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-3)])
-def test_sound_wave_768(fd6, orc, precision, tol):
+def sound_continuum(k, cs, nu, t, A):
+    """The same mode in the continuum (linearised equations, exact in time)."""
+    from scipy.linalg import expm
+    M = np.array([[0.0, k], [-cs * cs * k, -(4.0 / 3.0) * nu * k * k]])
+    return expm(M * t) @ np.array([A, 0.0])
+
+
+SOUND_N, SOUND_STEPS, SOUND_A, SOUND_K = 768, 1000, 1e-4, 4
+
+
+@pytest.fixture(scope="module")
+def sound_slab_ref(orc):
+    """Oracle runs of the exact 768 x 8 x 8 replica of the 768^3 x-profile
+    (the fields never vary in y and z), FP64 inputs and FP32-rounded inputs."""
+    slab = si.sound_wave_box(shape=(8, 8, SOUND_N), amplitude=SOUND_A, k=SOUND_K)
+    h = 2 * math.pi / SOUND_N
+    out = {}
+    for prec in ("fp64", "fp32"):
+        f = slab.fields if prec == "fp64" else si.as_float32_exact(slab.fields)
+        out[prec] = orc.rk3(f, slab.nu, slab.cs, h, h, h, slab.dt, "55p", SOUND_STEPS, 16)
+    return slab, out
+
+
+@pytest.mark.parametrize("precision,tol,tol_disc", [("fp64", 1e-10, 2e-7), ("fp32", 2e-3, 1e-4)])
+def test_sound_wave_768_1000_steps(fd6, sound_slab_ref, precision, tol, tol_disc):
+    """768^3 linear sound wave, 1000 steps (t = 3.27): the x-profile equals the
+    oracle's slab replica; every column is identical; the projections onto
+    sin 4x / cos 4x follow the fully discrete closed form to the O(A^2)
+    nonlinear floor; against the continuum the amplitude shows the RK3 loss
+    the closed forms predict (about 1.2e-6) and the phase agrees to 1e-7 rad."""
     import torch
-    n, nsteps = 768, 200
-    slab = si.sound_wave_box(shape=(8, 8, n))          # exact replica of the x-profile
-    full_dt = slab.dt
+    slab, ref_all = sound_slab_ref
+    ref = ref_all[precision]
+    n, A, k = SOUND_N, SOUND_A, SOUND_K
     h = 2 * math.pi / n
-    ref = orc.rk3(slab.fields if precision == "fp64" else si.as_float32_exact(slab.fields),
-                  slab.nu, slab.cs, h, h, h, full_dt, "55p", nsteps, 16)
     box = fd6.Box((n, n, n), precision)
-    box.set_params(slab.nu, slab.cs, h, h, h, full_dt)
+    box.set_params(slab.nu, slab.cs, h, h, h, slab.dt)
     x = torch.arange(n, dtype=torch.float64, device="cuda") * h
-    lnrho = (1e-4 * torch.sin(4 * x)).expand(n, n, n).contiguous()
+    lnrho = (A * torch.sin(k * x)).expand(n, n, n).contiguous()
     zero = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
     box.init_fields([lnrho, zero, zero, zero])
     del lnrho
-    box.step(nsteps)
+    box.step(SOUND_STEPS)
     out = box.get_fields_device()
-    lr = out[0]
-    ux = out[1]
+    box.close()
+    lr, ux = out[0], out[1]
     # every (y, z) column carries the same x-profile; uy and uz vanish in
     # exact arithmetic (the z-sweep's mixed-term accumulation leaves only a
     # rounding residue, while the oracle's direct stencil cancels exactly)
     assert float((lr - lr[0:1, 0:1, :]).abs().max()) == 0.0
     eps = 1e-14 if precision == "fp64" else 1e-6
-    assert float(out[2].abs().max()) <= eps * 1e-4 and float(out[3].abs().max()) <= eps * 1e-4
+    assert float(out[2].abs().max()) <= eps * A and float(out[3].abs().max()) <= eps * A
     prof = [lr[0, 0].cpu().numpy(), ux[0, 0].cpu().numpy()]
-    e = max(float(np.max(np.abs(prof[0] - ref[0][0, 0]))) / 1e-4,
-            float(np.max(np.abs(prof[1] - ref[1][0, 0]))) / 1e-4)
-    print(f"768^3 sound wave {precision}: profile err vs oracle slab {e:.3e}", flush=True)
+    del out, lr, ux
+    e = max(float(np.max(np.abs(prof[0] - ref[0][0, 0]))) / A,
+            float(np.max(np.abs(prof[1] - ref[1][0, 0]))) / A)
+    xs = np.arange(n) * h
+    L = 2 / n * float(np.sum(prof[0] * np.sin(k * xs)))
+    U = 2 / n * float(np.sum(prof[1] * np.cos(k * xs)))
+    Ld, Ud = sound_closed_form(k, h, slab.cs, slab.nu, slab.dt, SOUND_STEPS, A)
+    Lc, Uc = sound_continuum(k, slab.cs, slab.nu, SOUND_STEPS * slab.dt, A)
+    amp_loss = math.hypot(L, U) / math.hypot(Lc, Uc) - 1
+    amp_loss_disc = math.hypot(Ld, Ud) / math.hypot(Lc, Uc) - 1
+    dphase = math.atan2(U, L) - math.atan2(Uc, Lc)
+    print(f"768^3 sound wave {precision} x {SOUND_STEPS}: profile err vs oracle slab {e:.3e}, "
+          f"vs discrete ({(L - Ld) / A:.2e}, {(U - Ud) / A:.2e}), amplitude vs continuum "
+          f"{amp_loss:.3e} (closed form {amp_loss_disc:.3e}), phase {dphase:.2e}", flush=True)
     assert e <= tol
-    # projection onto sin(4x) / cos(4x) against the fully discrete closed form
-    L = 2 / n * float(np.sum(prof[0] * np.sin(4 * x.cpu().numpy())))
-    U = 2 / n * float(np.sum(prof[1] * np.cos(4 * x.cpu().numpy())))
-    Lc, Uc = sound_closed_form(4, h, slab.cs, slab.nu, full_dt, nsteps, 1e-4)
-    assert abs(L - Lc) <= 1e-3 * 1e-4 and abs(U - Uc) <= 1e-3 * 1e-4
+    assert abs(L - Ld) <= tol_disc * A and abs(U - Ud) <= tol_disc * A
+    assert -1.5e-6 <= amp_loss_disc <= -1.0e-6
+    assert abs(amp_loss - amp_loss_disc) <= (2e-7 if precision == "fp64" else 1e-4)
+    assert abs(dphase) <= (1e-7 if precision == "fp64" else 1e-4)
+
+
+def test_sound_wave_64_replica_1000_steps(fd6, orc):
+    """The 64^3 replica (same amplitude, k and nu, its own time step): the
+    full fields after 1000 steps against the FP64 oracle."""
+    w = si.sound_wave_box(64, amplitude=SOUND_A, k=SOUND_K)
+    ref = orc.rk3(w.fields, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", SOUND_STEPS, 16)
+    box = fd6.Box(w.shape, "fp64")
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(w.fields)
+    box.step(SOUND_STEPS)
+    out = box.get_fields()
+    box.close()
+    e = max(float(np.max(np.abs(a - b))) for a, b in zip(out, ref)) / SOUND_A
+    print(f"64^3 sound wave x {SOUND_STEPS}: err vs oracle {e:.3e}", flush=True)
+    assert e <= 1e-10
 
 
 def test_ensemble_64_boxes_bitwise(fd6):
