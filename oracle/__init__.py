@@ -56,10 +56,14 @@ def _load():
         lib.orc_rk3.restype = i
         lib.orc_rhs.argtypes = [i, i, i, dp, dp, dp, dp, d, d, d, d, d, i, dp, dp, dp, dp, i]
         lib.orc_rhs.restype = i
-        lib.orc_rk3_patch.argtypes = [i, dp, dp, dp, dp, d, d, d, d, d, d, i, i, dp]
+        lib.orc_rk3_patch.argtypes = [i, dp, dp, dp, dp, d, d, d, d, d, d, i, i, dp, dp, dp, dp]
         lib.orc_rk3_patch.restype = i
         lib.orc_reduce.argtypes = [i, i, i, dp, dp, dp, dp, d, d, d, dp]
         lib.orc_reduce.restype = i
+        lib.orc_set_forcing.argtypes = [dp]
+        lib.orc_set_forcing.restype = i
+        lib.orc_get_forcing_amplitude.argtypes = [dp]
+        lib.orc_get_forcing_amplitude.restype = None
         _lib = lib
     return _lib
 
@@ -74,6 +78,25 @@ def _fields(fields: Sequence[np.ndarray]):
     shape = out[0].shape
     assert len(out) == 4 and all(f.shape == shape for f in out) and len(shape) == 3
     return out, shape
+
+
+def set_forcing(forcing=None, cs=1.0, dt=1.0):
+    """External force of the momentum equation for every later call: one mode
+    of eq. (forcing) with wave vector k, unit vector e, magnitude f0 and phase,
+    given as ``{"k": (kx, ky, kz), "e": (ex, ey, ez), "f0": f0, "phase": phi}``
+    (cs and dt enter its normalisation); None: no force.  Returns the force
+    amplitude vector N f_k the oracle uses."""
+    lib = _load()
+    if forcing is None:
+        lib.orc_set_forcing(None)
+        return None
+    v = np.array(list(forcing["k"]) + list(forcing["e"]) +
+                 [forcing["f0"], forcing["phase"], cs, dt], dtype=np.float64)
+    if lib.orc_set_forcing(_ptr(v)) != 0:
+        raise ValueError("forcing: |k| = 0 or e parallel to k")
+    a = np.zeros(3)
+    lib.orc_get_forcing_amplitude(_ptr(a))
+    return a
 
 
 def rk3(fields, nu, cs, dx, dy, dz, dt, variant="55p", nsteps=1, threads=0):
@@ -132,9 +155,12 @@ def rk3_point(fields, center, nu, cs, dx, dy, dz, dt, variant="55p", nsteps=1):
     iy = (np.arange(j - m, j + m + 1) % ny)[None, :, None]
     ix = (np.arange(i - m, i + m + 1) % nx)[None, None, :]
     patch = [np.ascontiguousarray(f[iz, iy, ix], dtype=np.float64) for f in fields]
+    # coordinates of the patch points, wrapped as in the periodic box
+    coords = [np.ascontiguousarray(idx.ravel() * h, dtype=np.float64)
+              for idx, h in ((ix, dx), (iy, dy), (iz, dz))]
     out = np.zeros(4)
     rc = _load().orc_rk3_patch(m, *[_ptr(a) for a in patch], nu, cs, dx, dy, dz, dt,
-                               VARIANTS[variant], nsteps, _ptr(out))
+                               VARIANTS[variant], nsteps, *[_ptr(c) for c in coords], _ptr(out))
     if rc != 0:
         raise ValueError(f"orc_rk3_patch failed ({rc})")
     return out

@@ -17,9 +17,12 @@
  *     prefactor read as 1/(180 dx^2) (the printed 1/(180 dx) is dimensionally
  *     wrong; the moment sum 2*(270 - 27*4 + 2*9) = 360 needs dx^2)
  *   - bidiagonal mixed derivative, eq. (mixed_derivatives), Sec. 2.3
- *   - continuity eq. (continuity), momentum eq. (navierstokes) with f = 0 and
- *     the traceless rate-of-strain tensor eq. (tensor), Sec. 2.1; D/Dt is the
- *     convective derivative, so d/dt = D/Dt - u.grad
+ *   - continuity eq. (continuity), momentum eq. (navierstokes) and the
+ *     traceless rate-of-strain tensor eq. (tensor), Sec. 2.1; D/Dt is the
+ *     convective derivative, so d/dt = D/Dt - u.grad.  The external force f
+ *     is zero unless orc_set_forcing gives one Fourier mode of eq. (forcing),
+ *     Sec. 6, constant over a full step (the caller draws k, e and phi);
+ *     grid point (i, j, k) sits at x = (i dx, j dy, k dz)
  *   - 2N-storage RK3, eq. (2N-RK_scheme) and Algorithm 1, Sec. 2.4.  The paper
  *     does not print alpha/beta beyond alpha(1) = 0; the values used are the
  *     Williamson (1980) low-storage RK3 coefficients
@@ -194,6 +197,42 @@ typedef struct {
     double nu, cs, h[3];
 } phys_t;
 
+/* External force of eq. (navierstokes), one mode of eq. (forcing). */
+static int g_force_on = 0;
+static double g_force_k[3], g_force_a[3], g_force_phase;
+
+/* Switches the force on for every later call: in = (kx, ky, kz, ex, ey, ez,
+ * f0, phase, cs, dt).  Eq. (forcing): f(x) = Re{N f_k exp(i k.x + i phi)}
+ * with N = f0 cs sqrt(|k| cs / dt) and f_k = (k x e) / sqrt(|k|^2 - (k.e)^2),
+ * which is real, so f(x) = N f_k cos(k.x + phi).  NULL switches it off.
+ * Returns -1 (force off) if e is parallel to k or |k| = 0. */
+int orc_set_forcing(const double *in) {
+    g_force_on = 0;
+    if (!in) return 0;
+    const double *k = in, *e = in + 3;
+    const double f0 = in[6], phase = in[7], cs = in[8], dt = in[9];
+    const double kk = sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    const double ke = k[0] * e[0] + k[1] * e[1] + k[2] * e[2];
+    const double den2 = kk * kk - ke * ke;
+    if (!(kk > 0.0) || !(den2 > 0.0) || !(dt > 0.0)) return -1;
+    const double norm = f0 * cs * sqrt(kk * cs / dt);
+    const double den = sqrt(den2);
+    const double kxe[3] = {k[1] * e[2] - k[2] * e[1], k[2] * e[0] - k[0] * e[2],
+                           k[0] * e[1] - k[1] * e[0]};
+    for (int i = 0; i < 3; ++i) {
+        g_force_k[i] = k[i];
+        g_force_a[i] = norm * kxe[i] / den;
+    }
+    g_force_phase = phase;
+    g_force_on = 1;
+    return 0;
+}
+
+/* The amplitude vector N f_k in use (zeros when the force is off). */
+void orc_get_forcing_amplitude(double a[3]) {
+    for (int i = 0; i < 3; ++i) a[i] = g_force_on ? g_force_a[i] : 0.0;
+}
+
 typedef struct {
     const double *lnrho, *u[3];
     ptrdiff_t s[3]; /* strides along x, y, z */
@@ -205,7 +244,7 @@ typedef struct {
  * drops the (nu/3) grad(div u) term, which is the first pass of the 19-point
  * method (Sec. 4.2).  Also returns div u from first derivatives. */
 static void rhs_point(const state_view_t *v, size_t c, const phys_t *p, int with_graddiv,
-                      double r[4], double *div_out) {
+                      const double xyz[3], double r[4], double *div_out) {
     double g[3], J[3][3], u[3];
     for (int j = 0; j < 3; ++j) g[j] = op_d1(v->lnrho, c, v->s[j], p->h[j]);
     for (int i = 0; i < 3; ++i)
@@ -233,8 +272,14 @@ static void rhs_point(const state_view_t *v, size_t c, const phys_t *p, int with
                                : op_dmix(v->u[j], c, v->s[i], v->s[j], p->h[i], p->h[j]);
             visc += gd / 3.0;
         }
-        /* eq. (navierstokes) with f = 0 */
+        /* eq. (navierstokes) */
         r[1 + i] = -adv - p->cs * p->cs * g[i] + p->nu * visc;
+    }
+    if (g_force_on) {
+        const double arg = g_force_k[0] * xyz[0] + g_force_k[1] * xyz[1] +
+                           g_force_k[2] * xyz[2] + g_force_phase;
+        const double cphi = cos(arg);
+        for (int i = 0; i < 3; ++i) r[1 + i] += g_force_a[i] * cphi;
     }
     if (div_out) *div_out = div;
 }
@@ -309,8 +354,9 @@ static void substep55(box_t *b, const phys_t *p, double dt, int s) {
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
                 size_t c = gidx(g, i, j, k);
+                const double xyz[3] = {i * p->h[0], j * p->h[1], k * p->h[2]};
                 double r[4];
-                rhs_point(&v, c, p, 1, r, NULL);
+                rhs_point(&v, c, p, 1, xyz, r, NULL);
                 for (int q = 0; q < 4; ++q) b->w[q][c] = a * b->w[q][c] + dt * r[q];
             }
 #pragma omp parallel for schedule(static)
@@ -336,8 +382,9 @@ static void substep19(box_t *b, const phys_t *p, double dt, int s) {
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
                 size_t c = gidx(g, i, j, k);
+                const double xyz[3] = {i * p->h[0], j * p->h[1], k * p->h[2]};
                 double r[4], div;
-                rhs_point(&v, c, p, 0, r, &div);
+                rhs_point(&v, c, p, 0, xyz, r, &div);
                 b->d[c] = div;
                 for (int q = 0; q < 4; ++q) {
                     b->w[q][c] = a * b->w[q][c] + dt * r[q];
@@ -425,8 +472,9 @@ int orc_rhs(int nx, int ny, int nz, const double *lnrho, const double *ux, const
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 size_t gc = gidx(g, i, j, k);
+                const double xyz[3] = {i * dx, j * dy, k * dz};
                 double r[4], div;
-                rhs_point(&v, gc, &p, variant == VAR_55P, r, &div);
+                rhs_point(&v, gc, &p, variant == VAR_55P, xyz, r, &div);
                 if (variant == VAR_19P) b.d[gc] = div;
                 for (int q = 0; q < 4; ++q) out[q][cidx(g, i, j, k)] = r[q];
             }
@@ -450,12 +498,14 @@ int orc_rhs(int nx, int ny, int nz, const double *lnrho, const double *ux, const
 /* consumes R cells of the patch on every side (2R for the 19-point method,  */
 /* whose second pass differentiates the first pass's divergence), so a patch */
 /* of half-width m = nsteps * 3 * R (55p) or nsteps * 6 * R (19p) determines  */
-/* the centre exactly as the periodic run over the whole box does.           */
+/* the centre exactly as the periodic run over the whole box does.  px, py,  */
+/* pz: coordinates of the patch points along each axis (for the force).      */
 /* ------------------------------------------------------------------------ */
 
 int orc_rk3_patch(int m, const double *lnrho, const double *ux, const double *uy,
                   const double *uz, double nu, double cs, double dx, double dy, double dz,
-                  double dt, int variant, int nsteps, double out[4]) {
+                  double dt, int variant, int nsteps, const double *px, const double *py,
+                  const double *pz, double out[4]) {
     const int shrink = (variant == VAR_55P) ? R : 2 * R;
     if (variant != VAR_55P && variant != VAR_19P) return -1;
     if (nsteps < 1 || m < 3 * shrink * nsteps) return -1;
@@ -491,8 +541,9 @@ int orc_rk3_patch(int m, const double *lnrho, const double *ux, const double *uy
                         for (int j = a0; j < a1; ++j)
                             for (int i = a0; i < a1; ++i) {
                                 size_t c = ((size_t)k * n + j) * n + i;
+                                const double xyz[3] = {px[i], py[j], pz[k]};
                                 double r[4];
-                                rhs_point(&v, c, &p, 1, r, NULL);
+                                rhs_point(&v, c, &p, 1, xyz, r, NULL);
                                 for (int q = 0; q < 4; ++q) {
                                     w[q][c] = a * w[q][c] + dt * r[q];
                                     o[q][c] = f[q][c] + be * w[q][c];
@@ -505,8 +556,9 @@ int orc_rk3_patch(int m, const double *lnrho, const double *ux, const double *uy
                         for (int j = a0; j < a1; ++j)
                             for (int i = a0; i < a1; ++i) {
                                 size_t c = ((size_t)k * n + j) * n + i;
+                                const double xyz[3] = {px[i], py[j], pz[k]};
                                 double r[4], div;
-                                rhs_point(&v, c, &p, 0, r, &div);
+                                rhs_point(&v, c, &p, 0, xyz, r, &div);
                                 d[c] = div;
                                 for (int q = 0; q < 4; ++q) {
                                     w[q][c] = a * w[q][c] + dt * r[q];

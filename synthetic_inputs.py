@@ -193,3 +193,38 @@ def as_float32_exact(fields):
     """The FP32 values a float32 store of these fields holds, as float64 (round
     to nearest even, done on the host by numpy)."""
     return [np.asarray(f, dtype=np.float32).astype(np.float64) for f in fields]
+
+
+# ---------------------------------------------------------------------------
+# Random draws of the forcing (Sec. 6): the method picks, at every time step,
+# a wave vector from an isotropic set, a unit vector e perpendicular to it and
+# a phase.  These draws are inputs to both the library and the oracle; the
+# force itself (its normalisation and direction) is computed by each of them.
+# ---------------------------------------------------------------------------
+def forcing_wavevectors(kmin: float, kmax: float) -> np.ndarray:
+    """All integer wave vectors of a 2 pi periodic box with kmin <= |k| <= kmax."""
+    m = int(np.floor(kmax))
+    r = np.arange(-m, m + 1)
+    k = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    kk = np.linalg.norm(k, axis=1)
+    return k[(kk >= kmin) & (kk <= kmax) & (kk > 0)].astype(np.float64)
+
+
+def forcing_draws(nsteps: int, kmin: float, kmax: float, f0: float, seed: int = 0) -> List[dict]:
+    """Per time step: k uniformly from the isotropic set, e a uniformly random
+    unit vector perpendicular to k, phase uniform in [0, 2 pi)."""
+    ks = forcing_wavevectors(kmin, kmax)
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nsteps):
+        k = ks[rng.integers(len(ks))]
+        khat = k / np.linalg.norm(k)
+        t = np.array([1.0, 0.0, 0.0]) if abs(khat[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+        b1 = t - (t @ khat) * khat
+        b1 /= np.linalg.norm(b1)
+        b2 = np.cross(khat, b1)
+        th = rng.uniform(0.0, 2.0 * np.pi)
+        e = np.cos(th) * b1 + np.sin(th) * b2
+        out.append({"k": tuple(k), "e": tuple(e), "f0": f0,
+                    "phase": float(rng.uniform(0.0, 2.0 * np.pi))})
+    return out
