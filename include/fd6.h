@@ -175,6 +175,28 @@ int fd6_set_tile(fd6_box *box, int32_t tile);
  * do not depend on it (bit for bit).  FD6_EINVAL if zchunk < 0. */
 int fd6_set_zchunk(fd6_box *box, int32_t zchunk);
 
+/* External force of the momentum equation: one Fourier mode of eq.
+ * (forcing), Sec. 6,
+ *   f(x) = Re{ N f_k exp(i k.x + i phase) },  N = f0 cs sqrt(|k| cs / dt),
+ *   f_k = (k x e) / sqrt(|k|^2 - (k.e)^2),
+ * evaluated at grid point (i, j, k) as x = (i dx, j dy, k dz) and added to the
+ * momentum right-hand side of every substep until changed.  The method draws
+ * k (from an isotropic shell of wave vectors of the box), the unit vector e
+ * and the phase afresh at every time step; those draws are the caller's:
+ * call fd6_set_forcing before each fd6_rk3_step(box, 1).  k should be a wave
+ * vector of the periodic box (k_x nx dx a multiple of 2 pi, likewise y, z)
+ * for f to be periodic.  N uses the box's current cs and dt (fd6_set_params).
+ * f = NULL switches the force off.  FD6_EINVAL for non-finite values, k = 0,
+ * |e| != 1 (within 1e-6), e parallel to k, or f0 < 0.  Not available for the
+ * batched ensemble. */
+typedef struct {
+    double kx, ky, kz; /* wave vector (radians per unit length) */
+    double ex, ey, ez; /* unit vector, not parallel to k */
+    double f0;         /* magnitude */
+    double phase;      /* radians */
+} fd6_forcing;
+int fd6_set_forcing(fd6_box *box, const fd6_forcing *f);
+
 /* Graph mode (Algorithm 2 as one HIP graph per step): with enable != 0,
  * fd6_rk3_step and fd6_rk3_step_reduce capture one full step (three substeps,
  * and for the reducing variant the diagnostics of the last step, with d_out

@@ -30,7 +30,7 @@ ABI_SYMBOLS = (
     "fd6_set_stream", "fd6_set_params", "fd6_init_fields", "fd6_init_fields_device",
     "fd6_rk3_step", "fd6_rk3_step_reduce", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
     "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_zchunk", "fd6_set_graph",
-    "fd6_set_timing",
+    "fd6_set_forcing", "fd6_set_timing",
     "fd6_get_timing",
     "fd6_last_error", "fd6_batch_workspace_bytes", "fd6_batch_create", "fd6_batch_destroy",
     "fd6_batch_set_params", "fd6_batch_init_fields", "fd6_batch_set_schedule",
@@ -47,6 +47,10 @@ class Fd6Desc(ctypes.Structure):
 
 class Fd6Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("nu", "cs", "dx", "dy", "dz", "dt")]
+
+
+class Fd6Forcing(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("kx", "ky", "kz", "ex", "ey", "ez", "f0", "phase")]
 
 
 class Fd6Reductions(ctypes.Structure):
@@ -90,6 +94,7 @@ def _declare(lib):
         "fd6_set_tile": (I, [P, ctypes.c_int32]),
         "fd6_set_zchunk": (I, [P, ctypes.c_int32]),
         "fd6_set_graph": (I, [P, ctypes.c_int32]),
+        "fd6_set_forcing": (I, [P, ctypes.POINTER(Fd6Forcing)]),
         "fd6_last_error": (ctypes.c_char_p, [P]),
         "fd6_batch_workspace_bytes": (I, [ctypes.c_int32, ctypes.POINTER(Fd6Desc),
                                           ctypes.POINTER(ctypes.c_size_t)]),
@@ -268,6 +273,17 @@ class Box:
     def set_zchunk(self, zchunk: int):
         """z-chunk length of the sweep kernels (0: automatic)."""
         self._check(self.lib.fd6_set_zchunk(self.h, int(zchunk)), "fd6_set_zchunk")
+
+    def set_forcing(self, forcing=None):
+        """External force (one mode of eq. forcing) for the following steps:
+        ``{"k": (kx, ky, kz), "e": (ex, ey, ez), "f0": f0, "phase": phi}``, or
+        None to switch it off."""
+        if forcing is None:
+            self._check(self.lib.fd6_set_forcing(self.h, None), "fd6_set_forcing")
+            return
+        f = Fd6Forcing(*[float(v) for v in forcing["k"]], *[float(v) for v in forcing["e"]],
+                       float(forcing["f0"]), float(forcing["phase"]))
+        self._check(self.lib.fd6_set_forcing(self.h, ctypes.byref(f)), "fd6_set_forcing")
 
     def set_graph(self, enable: bool):
         """Replay each step as a captured HIP graph."""

@@ -261,6 +261,52 @@ hipError_t launch_reduce(const Geom& g, Fields4<T> f, double* partials, double* 
     return hipGetLastError();
 }
 
+namespace {
+// Writes the force descriptor and the per-plane factors of eq. (forcing).
+template <typename T>
+__global__ __launch_bounds__(256) void force_table_kernel(int nz, ForceDev<T>* dev, T* tab,
+                                                          double kx, double ky, double kz,
+                                                          double phase, double dx, double dy,
+                                                          double dz, double a0, double a1,
+                                                          double a2) {
+    for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+        double sn, cs;
+        sincos(kz * (k * dz) + phase, &sn, &cs);
+        tab[2 * k] = T(cs);
+        tab[2 * k + 1] = T(sn);
+    }
+    if (threadIdx.x == 0) {
+        ForceDev<T> d;
+        d.kx = kx;
+        d.ky = ky;
+        d.kz = kz;
+        d.phase = phase;
+        d.dx = dx;
+        d.dy = dy;
+        d.dz = dz;
+        d.a[0] = T(a0);
+        d.a[1] = T(a1);
+        d.a[2] = T(a2);
+        *dev = d;
+    }
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_force_table(const Geom& g, ForceDev<T>* dev, T* tab, const double k[3],
+                              double phase, const double h[3], const double a[3],
+                              hipStream_t s) {
+    hipLaunchKernelGGL(force_table_kernel<T>, dim3(1), dim3(256), 0, s, g.nz, dev, tab, k[0], k[1],
+                       k[2], phase, h[0], h[1], h[2], a[0], a[1], a[2]);
+    return hipGetLastError();
+}
+template hipError_t launch_force_table<float>(const Geom&, ForceDev<float>*, float*,
+                                              const double*, double, const double*, const double*,
+                                              hipStream_t);
+template hipError_t launch_force_table<double>(const Geom&, ForceDev<double>*, double*,
+                                               const double*, double, const double*,
+                                               const double*, hipStream_t);
+
 hipError_t launch_reduce_final(const double* partials, int nparts, double* result, double dV,
                                hipStream_t s) {
     hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kRedThreads), 0, s, partials, nparts,

@@ -50,6 +50,13 @@ struct fd6_box {
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_kernel, ev_ghost;
     std::vector<hipEvent_t> ev_pool;
+    // external force (eq. forcing): the caller's inputs, and whether the
+    // device descriptor and table still have to be written
+    bool force_on = false;
+    bool force_dirty = false;
+    fd6_forcing force{};
+    void* force_dev = nullptr;
+    void* force_tab = nullptr;
     // optional captured graphs of one full step, per starting parity; the
     // reducing variant also records its diagnostics target
     bool use_graph = false;
@@ -131,7 +138,8 @@ size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Plan {
     Geom g;
     size_t tsize, wsize;
-    size_t off_state[2][4], off_w[4], off_div, off_partials, off_result, off_staging, total;
+    size_t off_state[2][4], off_w[4], off_div, off_partials, off_result, off_force, off_staging,
+        total;
     long long staging_elems;
 };
 
@@ -192,6 +200,9 @@ int make_plan(const fd6_desc* d, Plan* p) {
     off += round_up((size_t)kFusedPartials * kReduceSlots * sizeof(double), kAlign);
     p->off_result = off;
     off += kAlign;
+    // force descriptor (one 256-byte block) and its per-plane table
+    p->off_force = off;
+    off += kAlign + round_up((size_t)2 * d->nz * sizeof(double), kAlign);
     const long long plane_c = (long long)d->nx * d->ny;
     long long st = (long long)d->nx * d->ny * d->nz;
     const long long cap = 1LL << 22;  // 32 MiB of FP64, at least one plane
@@ -321,11 +332,14 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
         b->ghosts_ok[b->cur] = true;
     }
     int nparts = 0;  // > 0: substep 3 wrote the diagnostics partials itself
+    const ForceArgs<T> fa{static_cast<const ForceDev<T>*>(b->force_dev),
+                          static_cast<const T*>(b->force_tab)};
+    const ForceArgs<T>* frc = b->force_on ? &fa : nullptr;
     if (b->desc.variant == FD6_55P) {
         double* parts = (red_out && s == 3) ? b->partials : nullptr;
         rc = timed(b, b->ev_kernel, [&]() -> int {
             HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->zchunk, parts,
-                                               kFusedPartials, &nparts, b->stream)));
+                                               kFusedPartials, &nparts, frc, b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;
@@ -333,7 +347,7 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
         T* dv = static_cast<T*>(b->div);
         rc = timed(b, b->ev_kernel, [&]() -> int {
             HIPCHK(b, (launch_pass19a<T, TW>(g, in, out, w, dv, c, rk, s, b->tile, b->zchunk,
-                                                b->stream)));
+                                             frc, b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;
@@ -362,6 +376,30 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
             HIPCHK(b, launch_reduce<T>(g, fields_of<T>(b->state[b->cur]), b->partials, red_out,
                                        dV, b->stream));
     }
+    return FD6_OK;
+}
+
+// Writes the force descriptor and table for the current parameters if the
+// force or the parameters changed since the last write (stream-ordered, and
+// never inside a captured step, so replays read the current force).
+template <typename T>
+int force_sync(fd6_box* b) {
+    if (!b->force_on || !b->force_dirty) return FD6_OK;
+    const fd6_forcing& f = b->force;
+    const fd6_params& pp = b->params;
+    const double k[3] = {f.kx, f.ky, f.kz}, e[3] = {f.ex, f.ey, f.ez};
+    const double kk = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    const double ke = k[0] * e[0] + k[1] * e[1] + k[2] * e[2];
+    // eq. (forcing): N = f0 cs sqrt(|k| cs / dt), f_k = (k x e) / sqrt(|k|^2 - (k.e)^2)
+    const double norm = f.f0 * pp.cs * std::sqrt(kk * pp.cs / pp.dt);
+    const double den = std::sqrt(kk * kk - ke * ke);
+    const double kxe[3] = {k[1] * e[2] - k[2] * e[1], k[2] * e[0] - k[0] * e[2],
+                           k[0] * e[1] - k[1] * e[0]};
+    const double a[3] = {norm * kxe[0] / den, norm * kxe[1] / den, norm * kxe[2] / den};
+    const double h[3] = {pp.dx, pp.dy, pp.dz};
+    HIPCHK(b, launch_force_table<T>(b->geom, static_cast<ForceDev<T>*>(b->force_dev),
+                                    static_cast<T*>(b->force_tab), k, f.phase, h, a, b->stream));
+    b->force_dirty = false;
     return FD6_OK;
 }
 
@@ -410,6 +448,8 @@ int capture_step(fd6_box* b, int parity, double* red_out, hipGraphExec_t* out) {
 
 template <typename T, typename TW>
 int do_steps(fd6_box* b, int nsteps, double* red_out = nullptr) {
+    int frc = force_sync<T>(b);
+    if (frc) return frc;
     if (!b->use_graph || b->timing) {
         for (int n = 0; n < nsteps; ++n) {
             int rc = one_step<T, TW>(b, n == nsteps - 1 ? red_out : nullptr);
@@ -442,7 +482,9 @@ int do_rhs(fd6_box* b, double* const out[4]) {
     // substep-1 arithmetic with dt = 1 leaves w = r; the result state is
     // discarded by not swapping back
     RKCoef<TW> rk{TW(0), TW(0), TW(1)};
-    int rc = do_substep<T, TW>(b, 1, rk);
+    int rc = force_sync<T>(b);
+    if (rc) return rc;
+    rc = do_substep<T, TW>(b, 1, rk);
     b->cur ^= 1;  // keep the original state current
     b->ghosts_ok[b->cur ^ 1] = false;
     if (rc) return rc;
@@ -873,6 +915,8 @@ int fd6_create(const fd6_desc* desc, void* d_ws, size_t bytes, void* stream, fd6
         b->div = b->ws + p.off_div;
         b->partials = reinterpret_cast<double*>(b->ws + p.off_partials);
         b->result = reinterpret_cast<double*>(b->ws + p.off_result);
+        b->force_dev = b->ws + p.off_force;
+        b->force_tab = b->ws + p.off_force + kAlign;
         b->staging = reinterpret_cast<double*>(b->ws + p.off_staging);
         b->staging_elems = p.staging_elems;
         *out = b;
@@ -898,7 +942,31 @@ int fd6_set_params(fd6_box* b, const fd6_params* p) {
         return FD6_EINVAL;
     b->params = *p;
     b->have_params = true;
-    b->drop_graphs();  // coefficients are baked into captured steps
+    b->drop_graphs();         // coefficients are baked into captured steps
+    b->force_dirty = true;    // the force amplitude depends on cs and dt
+    return FD6_OK;
+}
+
+int fd6_set_forcing(fd6_box* b, const fd6_forcing* f) {
+    if (!b) return FD6_EINVAL;
+    if (!f) {
+        if (b->force_on) b->drop_graphs();  // the captured steps add the force
+        b->force_on = false;
+        return FD6_OK;
+    }
+    const double v[8] = {f->kx, f->ky, f->kz, f->ex, f->ey, f->ez, f->f0, f->phase};
+    for (double x : v)
+        if (!std::isfinite(x)) return FD6_EINVAL;
+    const double kk2 = f->kx * f->kx + f->ky * f->ky + f->kz * f->kz;
+    const double ee = f->ex * f->ex + f->ey * f->ey + f->ez * f->ez;
+    const double ke = f->kx * f->ex + f->ky * f->ey + f->kz * f->ez;
+    if (!(kk2 > 0.0) || std::fabs(ee - 1.0) > 1e-6 || !(kk2 - ke * ke > 1e-12 * kk2) ||
+        f->f0 < 0.0)
+        return FD6_EINVAL;
+    if (!b->force_on) b->drop_graphs();
+    b->force = *f;
+    b->force_on = true;
+    b->force_dirty = true;
     return FD6_OK;
 }
 

@@ -78,7 +78,30 @@ struct Coef {
     T sg[3], sg4[3], kxy[3], mu[3], kp;
 };
 
+// External force of the momentum equation, one Fourier mode of eq. (forcing)
+// (Sec. 6): f(x) = a cos(k.x + phase), a = N f_k, with grid point (i, j, k)
+// at x = (i dx, j dy, k dz).  Lives in device memory so that a captured step
+// reads the force of the current time step.  The sweep kernels form
+// cos(k.x + phase) = cos(A) cos(B) - sin(A) sin(B) with A = kx x + ky y per
+// column (once per tile) and B = kz z + phase per plane from tab:
+// tab[2 k] = cos(kz k dz + phase), tab[2 k + 1] = sin(...), 0 <= k < nz.
+template <typename T>
+struct ForceDev {
+    double kx, ky, kz, phase;
+    double dx, dy, dz;
+    T a[3];
+};
+template <typename T>
+struct ForceArgs {
+    const ForceDev<T>* dev;
+    const T* tab;
+};
+
 // Host-side launchers (implemented in the .hip files).
+template <typename T>
+hipError_t launch_force_table(const Geom& g, ForceDev<T>* dev, T* tab, const double k[3],
+                              double phase, const double h[3], const double a[3],
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_ghost_fill(const Geom& g, Fields4<T> f, int nfields, hipStream_t s);
 
@@ -99,10 +122,12 @@ hipError_t launch_zero_w(const Geom& g, Fields4<TW> w, hipStream_t s);
 // most part_cap workgroups also writes one FP64 diagnostics partial per
 // workgroup (kReduceSlots doubles each) and sets *nparts to their number;
 // otherwise *nparts = 0 and the caller reduces separately.
+// frc != nullptr adds the external force to the momentum right-hand side.
 template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                             const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                            double* partials, int part_cap, int* nparts, hipStream_t st);
+                            double* partials, int part_cap, int* nparts,
+                            const ForceArgs<T>* frc, hipStream_t st);
 // Whether a kernel shape reads the ghost zone of its input (the z-sweep
 // shapes resolve the periodic images in their loader instead).
 bool substep55_reads_ghosts(int tile);
@@ -136,11 +161,11 @@ int batch55_blocks_per_cu(int tile);
 template <typename T, typename TW>
 hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,
                           const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                          hipStream_t st);
+                          const ForceArgs<T>* frc, hipStream_t st);
 template <typename T, typename TW>
 hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                                 T* div, const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
-                                int zchunk, hipStream_t st);
+                                int zchunk, const ForceArgs<T>* frc, hipStream_t st);
 template <typename T, typename TW>
 hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
                           const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,

@@ -27,10 +27,11 @@ __device__ __forceinline__ T d2_taps(const T* f, long long c, long long s, const
            w[3] * (f[c + 3 * s] + f[c - 3 * s]);
 }
 
-template <typename T, typename TW, int S>
+template <typename T, typename TW, int S, bool FRC>
 __global__ __launch_bounds__(256) void pass19a_kernel(Geom g, Fields4<T> in, Fields4<T> out,
                                                       Fields4<TW> w, T* __restrict__ dv,
-                                                      Coef<T> cf, RKCoef<TW> rk) {
+                                                      Coef<T> cf, RKCoef<TW> rk,
+                                                      ForceArgs<T> fa) {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int k = blockIdx.z;
@@ -73,6 +74,13 @@ __global__ __launch_bounds__(256) void pass19a_kernel(Geom g, Fields4<T> in, Fie
     for (int q = 0; q < 3; ++q) {
         const T adv = u[0] * J[q][0] + u[1] * J[q][1] + u[2] * J[q][2];
         r[1 + q] = (L[q] + two_nu * sg[q]) - cf.cs2 * gr[q] - adv;
+    }
+    if constexpr (FRC) {  // f = a cos(k.x + phase), eq. (forcing)
+        const ForceDev<T>* fd = fa.dev;
+        const T ph = T(cos(fd->kx * (i * fd->dx) + fd->ky * (j * fd->dy) + fd->kz * (k * fd->dz) +
+                           fd->phase));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) r[1 + q] += fd->a[q] * ph;
     }
     const long long cw = (long long)k * g.wplane + (long long)j * g.wpx + i;
 #pragma unroll
@@ -229,20 +237,24 @@ __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __res
 template <typename T, typename TW>
 hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* div,
                           const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                          hipStream_t st) {
+                          const ForceArgs<T>* frc, hipStream_t st) {
     if (tile != 0)
-        return launch_pass19a_sweep<T, TW>(g, in, out, w, div, c, rk, s, tile, zchunk, st);
+        return launch_pass19a_sweep<T, TW>(g, in, out, w, div, c, rk, s, tile, zchunk, frc, st);
     const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4), (unsigned)g.nz);
-    switch (s) {
-    case 1:
-        hipLaunchKernelGGL((pass19a_kernel<T, TW, 1>), grid, dim3(256), 0, st, g, in, out, w, div,
-                           c, rk);
-        break;
-    default:
-        hipLaunchKernelGGL((pass19a_kernel<T, TW, 2>), grid, dim3(256), 0, st, g, in, out, w, div,
-                           c, rk);
-        break;
-    }
+    const ForceArgs<T> fa = frc ? *frc : ForceArgs<T>{nullptr, nullptr};
+    auto go = [&](auto force) {
+        constexpr bool FRC = decltype(force)::value;
+        if (s == 1)
+            hipLaunchKernelGGL((pass19a_kernel<T, TW, 1, FRC>), grid, dim3(256), 0, st, g, in, out,
+                               w, div, c, rk, fa);
+        else
+            hipLaunchKernelGGL((pass19a_kernel<T, TW, 2, FRC>), grid, dim3(256), 0, st, g, in, out,
+                               w, div, c, rk, fa);
+    };
+    if (frc)
+        go(std::true_type{});
+    else
+        go(std::false_type{});
     return hipGetLastError();
 }
 
@@ -287,7 +299,7 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
 #define FD6_INST19(T, TW)                                                                       \
     template hipError_t launch_pass19a<T, TW>(const Geom&, Fields4<T>, Fields4<T>, Fields4<TW>, \
                                               T*, const Coef<T>&, const RKCoef<TW>&, int, int, \
-                                              int, hipStream_t);                               \
+                                              int, const ForceArgs<T>*, hipStream_t);          \
     template hipError_t launch_pass19b<T, TW>(const Geom&, const T*, Fields4<T>, Fields4<TW>,   \
                                               const Coef<T>&, const RKCoef<TW>&, int, int,     \
                                               int, hipStream_t);

@@ -9,13 +9,14 @@ namespace fd6 {
 template hipError_t launch_substep55<float, float>(const Geom&, Fields4<float>, Fields4<float>,
                                               Fields4<float>, const Coef<float>&,
                                               const RKCoef<float>&, int, int, int, double*, int,
-                                              int*, hipStream_t);
+                                              int*, const ForceArgs<float>*, hipStream_t);
 template hipError_t launch_batch55<float, float>(const BatchBox<float, float>*, const BatchItem*, int,
                                             int, int, int, int, float, float, hipStream_t);
 template int batch55_blocks_per_cu<float, float>(int);
 template hipError_t launch_pass19a_sweep<float, float>(const Geom&, Fields4<float>, Fields4<float>,
                                                   Fields4<float>, float*, const Coef<float>&,
-                                                  const RKCoef<float>&, int, int, int, hipStream_t);
+                                                  const RKCoef<float>&, int, int, int,
+                                                  const ForceArgs<float>*, hipStream_t);
 
 int substep55_tile_count() { return kNumTiles; }
 

@@ -102,10 +102,10 @@ __device__ __forceinline__ T mix_at(const T* f, long long c, long long sa, long 
     return acc;
 }
 
-template <typename T, typename TW, int S>
+template <typename T, typename TW, int S, bool FRC>
 __global__ __launch_bounds__(256) void substep55_direct(Geom g, Fields4<T> in, Fields4<T> out,
-                                                        Fields4<TW> w, Coef<T> cf,
-                                                        RKCoef<TW> rk) {
+                                                        Fields4<TW> w, Coef<T> cf, RKCoef<TW> rk,
+                                                        ForceArgs<T> fa) {
     const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int k = blockIdx.z;
@@ -134,6 +134,13 @@ __global__ __launch_bounds__(256) void substep55_direct(Geom g, Fields4<T> in, F
     L[2] += mix_at(in.f[1], c, s[0], s[2], cf.mw[1]) + mix_at(in.f[2], c, s[1], s[2], cf.mw[2]);
     T r[4];
     assemble_rhs(u, gr, J, L, cf.nu, cf.cs2, r);
+    if constexpr (FRC) {  // f = a cos(k.x + phase), eq. (forcing)
+        const ForceDev<T>* fd = fa.dev;
+        const T ph = T(cos(fd->kx * (i * fd->dx) + fd->ky * (j * fd->dy) + fd->kz * (k * fd->dz) +
+                           fd->phase));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) r[1 + q] += fd->a[q] * ph;
+    }
     const long long cw = (long long)k * g.wplane + (long long)j * g.wpx + i;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -157,6 +164,8 @@ struct SweepRegs {
     TW wq[2][4];     // RK3 register of the output point (PD = 2: loaded a step early)
     double red[5];   // fused diagnostics of the thread's column (RED): sum rho,
                      // sum rho u^2 / 2, sum lnrho, max u^2, non-finite count
+    T fc, fs;        // FRC: cos / sin(kx x + ky y) of the thread's column
+    T fa[3];         // FRC: force amplitude vector
 };
 
 // Memory operations of a plane step are never skipped by a branch: a step
@@ -215,13 +224,14 @@ __device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
     }
 }
 
-template <int PH, int S, int PD, bool LD, bool P19, bool RED, typename T, typename TW, int TX,
-          int TY, int NH>
+template <int PH, int S, int PD, bool LD, bool P19, bool RED, bool FRC, typename T, typename TW,
+          int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, TW, NH>& R,
                                            const SweepCtx<T, TX, TY, LD>& X, T* lds,
                                            lds_t<T> lds3, const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
-                                           const Coef<T>& cf, const RKCoef<TW>& rk) {
+                                           const Coef<T>& cf, const RKCoef<TW>& rk,
+                                           const T* ftab) {
     using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int W = Sh::W;
     const int t = t0 + PH;
@@ -338,6 +348,15 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         const T u[3] = {R.q[1][sl8(PH - 3)], R.q[2][sl8(PH - 3)], R.q[3][sl8(PH - 3)]};
         T r[4];
         assemble_rhs(u, gr, J, Lf, cf.nu, cf.cs2, r);
+        if constexpr (FRC) {
+            // f = a cos(k.x + phase) at the output point (eq. forcing); the
+            // plane index wraps for the steps without an output plane
+            const int ow = o < 0 ? o + g.nz : o;
+            const T cz = ftab[2 * ow], sz = ftab[2 * ow + 1];
+            const T ph = R.fc * cz - R.fs * sz;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) r[1 + i] += R.fa[i] * ph;
+        }
         // ghost corner (-3, -3) of output plane o
         const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
         T vout[4];
@@ -529,12 +548,13 @@ __device__ __forceinline__ void red_store_n(double v[5], double* part) {
 // RED: also reduce the FP64 diagnostics of the output and store this
 // workgroup's partial at part[blockIdx.x * kReduceSlots ...].
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool P19 = false,
-          bool RED = false>
+          bool RED = false, bool FRC = false>
 __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
                                            const Coef<T>& cf, const RKCoef<TW>& rk, int x0,
                                            int y0, int zb, int ze, T* lds, lds_t<T> lds3,
-                                           double* part = nullptr) {
+                                           double* part = nullptr,
+                                           ForceArgs<T> fa = ForceArgs<T>{nullptr, nullptr}) {
     using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int NH = Sh::NH;
     SweepCtx<T, TX, TY, LD> X;
@@ -554,6 +574,17 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         for (int s = 0; s < 8; ++s) R.L[i][s] = T(0);
 #pragma unroll
     for (int i = 0; i < 5; ++i) R.red[i] = 0.0;
+    if constexpr (FRC) {
+        const ForceDev<T>* fd = fa.dev;
+        const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+        const double ang = fd->kx * ((x0 + tx) * fd->dx) + fd->ky * ((y0 + ty) * fd->dy);
+        double sn, cs;
+        sincos(ang, &sn, &cs);
+        R.fc = T(cs);
+        R.fs = T(sn);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) R.fa[i] = fd->a[i];
+    }
 
     const int nplanes = (ze - zb) + 2 * kR;
     if constexpr (LD) {
@@ -569,64 +600,65 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         }
     }
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        sweep_step<0, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
-        sweep_step<1, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
-        sweep_step<2, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
-        sweep_step<3, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
-        sweep_step<4, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
-        sweep_step<5, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
-        sweep_step<6, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
-        sweep_step<7, S, PD, LD, P19, RED>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf,
-                                             rk);
+        sweep_step<0, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
+        sweep_step<1, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
+        sweep_step<2, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
+        sweep_step<3, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
+        sweep_step<4, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
+        sweep_step<5, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
+        sweep_step<6, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
+        sweep_step<7, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+                                                  dv, cf, rk, fa.tab);
     }
     if constexpr (RED) red_store_n<SweepShape<T, TX, TY, LD>::NW>(R.red, part);
 }
 
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
-                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap) {
+                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
     if (t.zb >= t.ze) return;
-    sweep_tile<T, TW, TX, TY, S, PD, LD>(g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds,
-                                     (lds_t<T>)lds);
+    sweep_tile<T, TW, TX, TY, S, PD, LD, false, false, FRC>(
+        g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
 }
 
 // Substep 3 with the FP64 diagnostics of the new state fused in: one partial
 // per workgroup (every workgroup of the grid has a non-empty chunk).
-template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
-                         RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, double* part) {
+                         RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, double* part,
+                         ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
-    sweep_tile<T, TW, TX, TY, 3, PD, LD, false, true>(g, in, out, w, nullptr, cf, rk, t.tx, t.ty,
-                                                     t.zb, t.ze, lds, (lds_t<T>)lds, part);
+    sweep_tile<T, TW, TX, TY, 3, PD, LD, false, true, FRC>(
+        g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, part, fa);
 }
 
 // Pass 1 of the 19-point method (Sec. 4.2, Algorithm 3): the same sweep
 // without the mixed-derivative terms, with nu lap u in place of the viscous
 // operator, and the divergence stored for pass 2.
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv, Coef<T> cf,
-                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap) {
+                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
     if (t.zb >= t.ze) return;
-    sweep_tile<T, TW, TX, TY, S, PD, LD, true>(g, in, out, w, dv, cf, rk, t.tx, t.ty, t.zb, t.ze,
-                                           lds, (lds_t<T>)lds);
+    sweep_tile<T, TW, TX, TY, S, PD, LD, true, false, FRC>(
+        g, in, out, w, dv, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
 }
 
 // Batched form: one persistent launch advances every box of an ensemble by
@@ -671,18 +703,18 @@ hipError_t launch_s(int s, dim3 grid, dim3 block, hipStream_t st, A... args) {
     return hipGetLastError();
 }
 
-template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool FRC>
 struct K55 {
     template <int S>
     struct at {
-        static constexpr auto fn = substep55_sweep<T, TW, TX, TY, S, PD, LD>;
+        static constexpr auto fn = substep55_sweep<T, TW, TX, TY, S, PD, LD, FRC>;
     };
 };
-template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool FRC>
 struct K19 {
     template <int S>
     struct at {
-        static constexpr auto fn = substep19_pass1<T, TW, TX, TY, S, PD, LD>;
+        static constexpr auto fn = substep19_pass1<T, TW, TX, TY, S, PD, LD, FRC>;
     };
 };
 template <typename T, typename TW, int TX, int TY, int PD, bool LD>
@@ -692,11 +724,11 @@ struct KBatch {
         static constexpr auto fn = substep55_batch<T, TW, TX, TY, S, PD, LD>;
     };
 };
-template <typename T, typename TW>
+template <typename T, typename TW, bool FRC>
 struct KDirect {
     template <int S>
     struct at {
-        static constexpr auto fn = substep55_direct<T, TW, S>;
+        static constexpr auto fn = substep55_direct<T, TW, S, FRC>;
     };
 };
 
@@ -706,64 +738,75 @@ struct KDirect {
 template <typename T, typename TW>
 hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                             const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                            double* partials, int part_cap, int* nparts, hipStream_t st) {
+                            double* partials, int part_cap, int* nparts,
+                            const ForceArgs<T>* frc, hipStream_t st) {
     if (nparts) *nparts = 0;
-    return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
-        constexpr TileCfg k = kTiles[decltype(I)::value];
-        if constexpr (k.tx == 0) {
-            const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4),
-                            (unsigned)g.nz);
-            return launch_s<KDirect<T, TW>::template at>(s, grid, dim3(256), st, g, in, out, w,
-                                                         c, rk);
-        } else {
-            const int res =
-                resident_blocks<K55<T, TW, k.tx, k.ty, k.pd, k.ld>::template at<2>::fn>(k.tx * k.ty);
-            const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
-            // fuse only where the extra accumulators cost no occupancy
-            static const bool fuse_ok = [] {
-                int a = 0, b = 0;
-                const int blk = k.tx * k.ty;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &a, substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld>, blk, 0) !=
-                        hipSuccess ||
-                    hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                        &b, substep55_sweep<T, TW, k.tx, k.ty, 3, k.pd, k.ld>, blk, 0) !=
-                        hipSuccess)
-                    return false;
-                return a >= b && a > 0;
-            }();
-            if (s == 3 && partials && nparts && fuse_ok && sg.blocks <= part_cap) {
-                hipLaunchKernelGGL((substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld>),
-                                   dim3(sg.blocks), dim3(k.tx * k.ty), 0, st, g, in, out, w, c,
-                                   rk, sg.ntx, sg.nty, sg.zlen, xcd_remap(), partials);
-                *nparts = sg.blocks;
-                return hipGetLastError();
+    const ForceArgs<T> fa = frc ? *frc : ForceArgs<T>{nullptr, nullptr};
+    auto go = [&](auto force) -> hipError_t {
+        constexpr bool FRC = decltype(force)::value;
+        return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
+            constexpr TileCfg k = kTiles[decltype(I)::value];
+            if constexpr (k.tx == 0) {
+                const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4),
+                                (unsigned)g.nz);
+                return launch_s<KDirect<T, TW, FRC>::template at>(s, grid, dim3(256), st, g, in,
+                                                                  out, w, c, rk, fa);
+            } else {
+                using K = K55<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>;
+                const int res = resident_blocks<K::template at<2>::fn>(k.tx * k.ty);
+                const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
+                // fuse only where the extra accumulators cost no occupancy
+                static const bool fuse_ok = [] {
+                    int a = 0, b = 0;
+                    const int blk = k.tx * k.ty;
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &a, substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>, blk,
+                            0) != hipSuccess ||
+                        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &b, substep55_sweep<T, TW, k.tx, k.ty, 3, k.pd, k.ld, FRC>, blk, 0) !=
+                            hipSuccess)
+                        return false;
+                    return a >= b && a > 0;
+                }();
+                if (s == 3 && partials && nparts && fuse_ok && sg.blocks <= part_cap) {
+                    hipLaunchKernelGGL((substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>),
+                                       dim3(sg.blocks), dim3(k.tx * k.ty), 0, st, g, in, out, w,
+                                       c, rk, sg.ntx, sg.nty, sg.zlen, xcd_remap(), partials, fa);
+                    *nparts = sg.blocks;
+                    return hipGetLastError();
+                }
+                return launch_s<K::template at>(s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in,
+                                                out, w, c, rk, sg.ntx, sg.nty, sg.zlen,
+                                                xcd_remap(), fa);
             }
-            return launch_s<K55<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
-                s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in, out, w, c, rk, sg.ntx, sg.nty,
-                sg.zlen, xcd_remap());
-        }
-    });
+        });
+    };
+    return frc ? go(std::true_type{}) : go(std::false_type{});
 }
 
 // Pass 1 of the 19-point method in a z-sweep shape (tile >= 1).
 template <typename T, typename TW>
 hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                                 T* dv, const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
-                                int zchunk, hipStream_t st) {
-    return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
-        constexpr TileCfg k = kTiles[decltype(I)::value];
-        if constexpr (k.tx == 0) {
-            return hipErrorInvalidValue;
-        } else {
-            const int res =
-                resident_blocks<K19<T, TW, k.tx, k.ty, k.pd, k.ld>::template at<2>::fn>(k.tx * k.ty);
-            const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
-            return launch_s<K19<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
-                s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in, out, w, dv, c, rk, sg.ntx,
-                sg.nty, sg.zlen, xcd_remap());
-        }
-    });
+                                int zchunk, const ForceArgs<T>* frc, hipStream_t st) {
+    const ForceArgs<T> fa = frc ? *frc : ForceArgs<T>{nullptr, nullptr};
+    auto go = [&](auto force) -> hipError_t {
+        constexpr bool FRC = decltype(force)::value;
+        return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
+            constexpr TileCfg k = kTiles[decltype(I)::value];
+            if constexpr (k.tx == 0) {
+                return hipErrorInvalidValue;
+            } else {
+                using K = K19<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>;
+                const int res = resident_blocks<K::template at<2>::fn>(k.tx * k.ty);
+                const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
+                return launch_s<K::template at>(s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in,
+                                                out, w, dv, c, rk, sg.ntx, sg.nty, sg.zlen,
+                                                xcd_remap(), fa);
+            }
+        });
+    };
+    return frc ? go(std::true_type{}) : go(std::false_type{});
 }
 
 template <typename T, typename TW>

@@ -110,6 +110,18 @@ def test_create_validation_and_state_machine(pkg):
         assert lib.fd6_set_tile(h, -1) == -1
         assert lib.fd6_set_tile(h, 0) == 0
         assert lib.fd6_set_graph(h, 1) == 0 and lib.fd6_set_graph(h, 0) == 0
+        # forcing validation (host only)
+        F = pkg.Fd6Forcing
+        good_f = F(1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.01, 0.5)
+        assert lib.fd6_set_forcing(h, ctypes.byref(good_f)) == 0
+        assert lib.fd6_set_forcing(h, None) == 0
+        for bad in (F(0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.01, 0.5),      # k = 0
+                    F(1.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.01, 0.5),      # e parallel to k
+                    F(1.0, 0.0, 0.0, 0.0, 2.0, 0.0, 0.01, 0.5),      # |e| != 1
+                    F(1.0, 0.0, 0.0, 0.0, 1.0, 0.0, -0.01, 0.5),     # f0 < 0
+                    F(1.0, float("nan"), 0.0, 0.0, 1.0, 0.0, 0.01, 0.5)):
+            assert lib.fd6_set_forcing(h, ctypes.byref(bad)) == -1
+        assert lib.fd6_set_forcing(None, ctypes.byref(good_f)) == -1
         assert lib.fd6_set_graph(None, 1) == -1
         assert lib.fd6_set_zchunk(h, -1) == -1
         assert lib.fd6_set_zchunk(h, 0) == 0 and lib.fd6_set_zchunk(h, 10 ** 6) == 0
