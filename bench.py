@@ -169,6 +169,42 @@ def batch_form(torch, fd6, si, steps):
             "all_finite": all(r["nonfinite"] == 0 for r in red)}
 
 
+def forced_form(torch, fd6, si, steps):
+    """The forced-turbulence configuration of Sec. 6: 19-point method, 256^3,
+    nu = 1.4e-4, FP32, a new forcing mode drawn every step (isotropic shell
+    1 <= |k| <= 3, f0 = 0.02), next to the same steps without the force."""
+    n = 256
+    w = si.fourier_box(n, seed=0, amplitude=0.1, kmax=16.0, nu=1.4e-4)
+    draws = si.forcing_draws(steps + 2, 1.0, 3.0, 0.02, seed=0)
+    dev = [torch.from_numpy(f).cuda() for f in w.fields]
+    box = fd6.Box(w.shape, "fp32", "19p")
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    from paper_1707_08900_amd import tune as tuner
+    box.init_fields(dev)
+    tuned = tuner.tune(box, steps=2, use_cache=False)
+    res = {}
+    for forced in (True, False):
+        box.init_fields(dev)
+        box.set_forcing(draws[0] if forced else None)
+        box.step(2)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(box.stream)
+        for s in range(steps):
+            if forced:
+                box.set_forcing(draws[2 + s])
+            box.step(1)
+        e1.record(box.stream)
+        e1.synchronize()
+        res[forced] = e0.elapsed_time(e1) / steps
+    box.close()
+    return {"updates_per_s": n ** 3 / (res[True] * 1e-3), "ms_per_step": res[True],
+            "unforced_ms_per_step": res[False], "schedule": {"tile": tuned["tile"],
+                                                             "zchunk": tuned["zchunk"]},
+            "workload": "256^3, 19-point, FP32, nu = 1.4e-4, force drawn every step from "
+                        "1 <= |k| <= 3, f0 = 0.02"}
+
+
 def cpu_baseline(orc, si, w, threads):
     """FP64 oracle rate on a bounded sample of the workload: its first 128
     z-planes as a periodic 512 x 512 x 128 box, one full RK3 step."""
@@ -314,6 +350,12 @@ def main():
         for k, e in forms.items():
             if k != "fp32":
                 e["speed_vs_fp64_55p"] = e["updates_per_s"] / base64
+
+    if not a.no_forms:
+        forms["forced_fp32_19p_256"] = forced_form(torch, fd6, si, max(10, a.steps // 2))
+        ff = forms["forced_fp32_19p_256"]
+        log(f"forced 19p 256^3: {ff['ms_per_step']:.3f} ms/step with a new force each step, "
+            f"{ff['unforced_ms_per_step']:.3f} ms/step unforced")
 
     if not a.no_batch:
         forms["batched_fp32"] = batch_form(torch, fd6, si, max(10, a.steps // 2))

@@ -228,3 +228,43 @@ def forcing_draws(nsteps: int, kmin: float, kmax: float, f0: float, seed: int = 
         out.append({"k": tuple(k), "e": tuple(e), "f0": f0,
                     "phase": float(rng.uniform(0.0, 2.0 * np.pi))})
     return out
+
+
+def explosion_box(n: int = 64, nu: float = 5e-3, u_ampl: float = 1.0, d_shell: float = 0.2,
+                  r_shell: float = 0.8) -> Workload:
+    """Radial kinetic explosion of Sec. 6: rho = 1 (lnrho = 0) and
+    u = u_ampl exp(-(r - r_shell)^2 / (2 d_shell^2)) e_r about the domain
+    centre (pi, pi, pi), which is grid point n / 2 for even n.  (The printed
+    exponent lacks its minus sign; the Gaussian shell decays away from
+    r_shell.)"""
+    h = spacing(n)
+    c = np.arange(n) * h - math.pi
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    r = np.sqrt(x * x + y * y + z * z)
+    prof = u_ampl * np.exp(-((r - r_shell) ** 2) / (2.0 * d_shell ** 2))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        inv = np.where(r > 0, 1.0 / r, 0.0)
+    fields = [np.zeros((n, n, n)), prof * x * inv, prof * y * inv, prof * z * inv]
+    return _make(f"explosion {n}^3", (n, n, n), fields, nu,
+                 meta={"u_ampl": u_ampl, "d_shell": d_shell, "r_shell": r_shell})
+
+
+def axis_line_integrals(field: np.ndarray) -> np.ndarray:
+    """Line integrals of a field along the 7 axes through the centre of an
+    even-sized cubic 2 pi box (x, y, z and the 4 body diagonals), over
+    r <= pi on every axis, by the trapezoid rule with the point spacing of
+    the axis (delta on the coordinate axes, sqrt(3) delta on the diagonals).
+    The grid cannot give every axis the same extent, so fields with a
+    background should have it subtracted first."""
+    n = field.shape[0]
+    c = n // 2
+    h = spacing(n)
+    m = np.arange(-c, c + 1)
+    out = []
+    for step, dirs in ((h, ((0, 0, 1), (0, 1, 0), (1, 0, 0))),
+                       (math.sqrt(3.0) * h, ((1, 1, 1), (1, 1, -1), (1, -1, 1), (1, -1, -1)))):
+        mm = m[np.abs(m) * step <= math.pi + 1e-12]
+        for dz, dy, dx in dirs:
+            vals = field[(c + dz * mm) % n, (c + dy * mm) % n, (c + dx * mm) % n]
+            out.append(step * float(np.sum(vals) - 0.5 * (vals[0] + vals[-1])))
+    return np.array(out)
