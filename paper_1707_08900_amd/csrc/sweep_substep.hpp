@@ -351,8 +351,13 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         if constexpr (FRC) {
             // f = a cos(k.x + phase) at the output point (eq. forcing); the
             // plane index wraps for the steps without an output plane
+            // the table is read-only during the kernel: reading it through the
+            // constant address space makes these scalar loads, which keep out
+            // of the vector-memory counter the sweep's pipeline depends on
             const int ow = o < 0 ? o + g.nz : o;
-            const T cz = ftab[2 * ow], sz = ftab[2 * ow + 1];
+            const __attribute__((address_space(4))) T* ct =
+                (const __attribute__((address_space(4))) T*)ftab;
+            const T cz = ct[2 * ow], sz = ct[2 * ow + 1];
             const T ph = R.fc * cz - R.fs * sz;
 #pragma unroll
             for (int i = 0; i < 3; ++i) r[1 + i] += R.fa[i] * ph;
