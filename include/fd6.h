@@ -163,7 +163,10 @@ int fd6_rhs(fd6_box *box, double *r_lnrho, double *r_ux, double *r_uy, double *r
  * thread per point with every tap read through the caches from the ghost
  * zone, which a separate pass refreshes; 1 .. fd6_tile_count()-1 = z-sweep
  * kernels (periodic images resolved by their loaders, no ghost pass) with
- * different xy tile shapes and load pipelines.  Results agree up to rounding
+ * different xy tile shapes, load pipelines and cache policies (most shapes
+ * stream the new state and the RK register past the caches; the last ones
+ * keep them cached, which pays when the whole state fits in the device's
+ * last-level cache).  Results agree up to rounding
  * order (the z-sweep shapes bit for bit with each other); the choice only
  * changes speed (see the autotuner).  Default: 2. */
 int fd6_tile_count(void);

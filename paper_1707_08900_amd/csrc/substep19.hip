@@ -141,7 +141,7 @@ __device__ __forceinline__ void pass2_prefetch(Pass2Regs<T, NH>& R,
     for (int h = 0; h < NH; ++h) R.ph[h] = bload((T*)nullptr, rs, X.goff_h[h]);
 }
 
-template <int PH, int S, typename T, typename TW, int TX, int TY, int NH>
+template <int PH, int S, bool NT, typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Regs<T, NH>& R,
                                            const SweepCtx<T, TX, TY>& X, T* lds, const Geom& g,
                                            const T* dv, const Fields4<T>& out,
@@ -157,14 +157,15 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
     const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
     const unsigned ob = outstep ? X.plane_bytes : 0u;
     const unsigned wb = outstep ? X.wplane_bytes : 0u;
+    constexpr int CP = NT ? kNonTemporal : 0;
     T ov[3] = {T(0), T(0), T(0)};
     TW wv[3] = {TW(0), TW(0), TW(0)};
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        ov[i] = bload((T*)nullptr, plane_rsrc(out.f[1 + i] + ocorner, ob), X.lane_o);
+        ov[i] = bload<CP>((T*)nullptr, plane_rsrc(out.f[1 + i] + ocorner, ob), X.lane_o);
         if constexpr (S != 3)
-            wv[i] = bload((TW*)nullptr, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, wb),
-                          X.lane_w);
+            wv[i] = bload<CP>((TW*)nullptr,
+                              plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, wb), X.lane_w);
     }
     T* buf = lds + (PH & 1) * Sh::FS;
     const int ci = (threadIdx.x / TX + kR) * W + (threadIdx.x % TX + kR);
@@ -191,15 +192,15 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
         for (int i = 0; i < 3; ++i) {
             const TW tq = cgd * TW(gd[i]);
             if constexpr (S != 3)
-                bstore(wv[i] + tq, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, wb),
-                       X.lane_w);
-            bstore(T(TW(ov[i]) + rk.beta * tq), plane_rsrc(out.f[1 + i] + ocorner, ob),
-                   X.lane_o);
+                bstore<CP>(wv[i] + tq, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, wb),
+                           X.lane_w);
+            bstore<CP>(T(TW(ov[i]) + rk.beta * tq), plane_rsrc(out.f[1 + i] + ocorner, ob),
+                       X.lane_o);
         }
     }
 }
 
-template <typename T, typename TW, int TX, int TY, int S>
+template <typename T, typename TW, int TX, int TY, int S, bool NT>
 __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __restrict__ dv,
                                                           Fields4<T> out, Fields4<TW> w,
                                                           Coef<T> cf, RKCoef<TW> rk, TW cgd,
@@ -221,14 +222,14 @@ __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __res
     const int nplanes = (tl.ze - zb) + 2 * kR;
     pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, zb - kR), X.plane_bytes);
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        pass2_step<0, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<1, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<2, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<3, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<4, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<5, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<6, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<7, S>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<0, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<1, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<2, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<3, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<4, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<5, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<6, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<7, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
     }
 }
 
@@ -273,22 +274,23 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
             hipLaunchKernelGGL((pass19b_kernel<T, TW>), grid, dim3(256), 0, st, g, div, out, w, c,
                                rk, cgd);
         } else {
-            const int res = resident_blocks<substep19_pass2<T, TW, k.tx, k.ty, 2>>(k.tx * k.ty);
+            const int res =
+                resident_blocks<substep19_pass2<T, TW, k.tx, k.ty, 2, k.nt>>(k.tx * k.ty);
             const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
             const dim3 grid(sg.blocks), block(k.tx * k.ty);
             const int rm = xcd_remap();
             switch (s) {
             case 1:
-                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 1>), grid, block, 0, st, g,
-                                   div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 1, k.nt>), grid, block, 0,
+                                   st, g, div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
                 break;
             case 2:
-                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 2>), grid, block, 0, st, g,
-                                   div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 2, k.nt>), grid, block, 0,
+                                   st, g, div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
                 break;
             default:
-                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 3>), grid, block, 0, st, g,
-                                   div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 3, k.nt>), grid, block, 0,
+                                   st, g, div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
                 break;
             }
         }

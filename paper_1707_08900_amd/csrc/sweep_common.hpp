@@ -23,17 +23,27 @@ template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* p, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, (int)bytes, kBufFlags);
 }
+// Cache policy of an access (the instruction's cache-policy field): 0 keeps
+// the default, kNonTemporal marks a stream whose lines are not reused before
+// eviction (the new state and the RK register: each is touched once per
+// substep).
+constexpr int kNonTemporal = 2;
+
+template <int CP = 0>
 __device__ __forceinline__ float bload(float*, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, CP));
 }
+template <int CP = 0>
 __device__ __forceinline__ double bload(double*, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, CP));
 }
+template <int CP = 0>
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, CP);
 }
 
 // LD = false: the next plane is loaded into registers and written to LDS by
@@ -222,11 +232,14 @@ __device__ __forceinline__ TileXY sweep_tile_of(const Geom& g, int TX, int TY, i
 struct TileCfg {
     int tx, ty, pd;
     bool ld;
+    bool nt;  // new state and RK register streamed past the caches
 };
 constexpr TileCfg kTiles[] = {
-    {0, 0, 1, false},   {64, 4, 1, false}, {64, 8, 1, false}, {128, 4, 1, false},
-    {32, 8, 1, false},  {64, 4, 2, false}, {64, 8, 2, false}, {128, 4, 2, false},
-    {32, 8, 2, false},  {64, 8, 1, true},  {64, 8, 4, false}};
+    {0, 0, 1, false, false},  {64, 4, 1, false, true},  {64, 8, 1, false, true},
+    {128, 4, 1, false, true}, {32, 8, 1, false, true},  {64, 4, 2, false, true},
+    {64, 8, 2, false, true},  {128, 4, 2, false, true}, {32, 8, 2, false, true},
+    {64, 8, 1, true, true},   {64, 8, 4, false, true},  {64, 8, 1, false, false},
+    {64, 8, 2, false, false}, {32, 8, 2, false, false}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // Calls f(std::integral_constant<int, tile>) so that f can use kTiles[tile]

@@ -190,13 +190,13 @@ __device__ __forceinline__ void sweep_prefetch(SweepRegs<T, TW, NH>& R,
     }
 }
 
-template <int RS, typename T, typename TW, int NH>
+template <int RS, bool NT, typename T, typename TW, int NH>
 __device__ __forceinline__ void load_w(SweepRegs<T, TW, NH>& R, const Fields4<TW>& w,
                                        const Geom& g, int o, unsigned wplane_bytes,
                                        unsigned lane_w) {
 #pragma unroll
     for (int f = 0; f < 4; ++f)
-        R.wq[RS][f] = bload((TW*)nullptr,
+        R.wq[RS][f] = bload<NT ? kNonTemporal : 0>((TW*)nullptr,
                             plane_rsrc(w.f[f] + (long long)o * g.wplane, wplane_bytes), lane_w);
 }
 
@@ -224,7 +224,8 @@ __device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
     }
 }
 
-template <int PH, int S, int PD, bool LD, bool P19, bool RED, bool FRC, typename T, typename TW,
+template <int PH, int S, int PD, bool LD, bool NT, bool P19, bool RED, bool FRC, typename T,
+          typename TW,
           int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, TW, NH>& R,
                                            const SweepCtx<T, TX, TY, LD>& X, T* lds,
@@ -253,9 +254,9 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         if constexpr (S != 1) {
             if constexpr (PD >= 2) {
                 const bool next_out = t + 1 >= 2 * kR && t + 1 < nplanes;
-                load_w<(PH + 1) & 1>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u, X.lane_w);
+                load_w<(PH + 1) & 1, NT>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u, X.lane_w);
             } else {
-                load_w<0>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
+                load_w<0, NT>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
             }
         }
         // prefetched plane p -> LDS buffer (PH & 1)
@@ -277,7 +278,7 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         sweep_dma<T, TX, TY>(X, in, plane_corner(g, p + 1), lds3 + ((PH + 1) & 1) * 4 * Sh::FS,
                              t + 1 < nplanes ? X.plane_bytes : 0u);
         if constexpr (S != 1) {
-            load_w<0>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
+            load_w<0, NT>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
         }
     }
 
@@ -370,9 +371,10 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             TW wv = S == 1 ? TW(0) : R.wq[WS][f];
             const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv, rk);
             vout[f] = v;
-            bstore(v, plane_rsrc(out.f[f] + ocorner, ob), X.lane_o);
+            bstore<NT ? kNonTemporal : 0>(v, plane_rsrc(out.f[f] + ocorner, ob), X.lane_o);
             if constexpr (S != 3)
-                bstore(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, wb), X.lane_w);
+                bstore<NT ? kNonTemporal : 0>(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, wb),
+                                              X.lane_w);
         }
         // 19-point pass 1 also stores the divergence for pass 2
         if constexpr (P19)
@@ -552,8 +554,8 @@ __device__ __forceinline__ void red_store_n(double v[5], double* part) {
 
 // RED: also reduce the FP64 diagnostics of the output and store this
 // workgroup's partial at part[blockIdx.x * kReduceSlots ...].
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool P19 = false,
-          bool RED = false, bool FRC = false>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT,
+          bool P19 = false, bool RED = false, bool FRC = false>
 __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
                                            const Coef<T>& cf, const RKCoef<TW>& rk, int x0,
@@ -605,27 +607,27 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         }
     }
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        sweep_step<0, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<0, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
-        sweep_step<1, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<1, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
-        sweep_step<2, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<2, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
-        sweep_step<3, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<3, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
-        sweep_step<4, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<4, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
-        sweep_step<5, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<5, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
-        sweep_step<6, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<6, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
-        sweep_step<7, S, PD, LD, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
+        sweep_step<7, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
                                                   dv, cf, rk, fa.tab);
     }
     if constexpr (RED) red_store_n<SweepShape<T, TX, TY, LD>::NW>(R.red, part);
 }
 
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool FRC>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
                      RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, ForceArgs<T> fa) {
@@ -633,13 +635,13 @@ void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
     if (t.zb >= t.ze) return;
-    sweep_tile<T, TW, TX, TY, S, PD, LD, false, false, FRC>(
+    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, false, false, FRC>(
         g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
 }
 
 // Substep 3 with the FP64 diagnostics of the new state fused in: one partial
 // per workgroup (every workgroup of the grid has a non-empty chunk).
-template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool FRC>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
                          RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, double* part,
@@ -647,14 +649,14 @@ void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, C
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
-    sweep_tile<T, TW, TX, TY, 3, PD, LD, false, true, FRC>(
+    sweep_tile<T, TW, TX, TY, 3, PD, LD, NT, false, true, FRC>(
         g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, part, fa);
 }
 
 // Pass 1 of the 19-point method (Sec. 4.2, Algorithm 3): the same sweep
 // without the mixed-derivative terms, with nu lap u in place of the viscous
 // operator, and the divergence stored for pass 2.
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool FRC>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv, Coef<T> cf,
                      RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, ForceArgs<T> fa) {
@@ -662,7 +664,7 @@ void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
     if (t.zb >= t.ze) return;
-    sweep_tile<T, TW, TX, TY, S, PD, LD, true, false, FRC>(
+    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, true, false, FRC>(
         g, in, out, w, dv, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
 }
 
@@ -673,7 +675,7 @@ void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv
 // that XCD's L2.  Per-box geometry, pointers, coefficients and time step come
 // from device memory, so a captured graph never needs re-capture when they
 // change.  Per point the arithmetic is the single-box kernel's.
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT>
 __global__ __launch_bounds__(TX* TY)
 void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
                      const BatchItem* __restrict__ items, int nitems, int parity, TW alpha,
@@ -691,8 +693,8 @@ void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
         const Fields4<T> in = bx->st[parity], out = bx->st[parity ^ 1];
         const Fields4<TW> w = bx->w;
         const RKCoef<TW> rk{alpha, beta, bx->dt};
-        sweep_tile<T, TW, TX, TY, S, PD, LD>(g, in, out, w, nullptr, cf, rk, wi.x0, wi.y0, wi.zb,
-                                         wi.ze, lds, (lds_t<T>)lds);
+        sweep_tile<T, TW, TX, TY, S, PD, LD, NT>(g, in, out, w, nullptr, cf, rk, wi.x0, wi.y0,
+                                             wi.zb, wi.ze, lds, (lds_t<T>)lds);
         __syncthreads();  // the next item's first LDS write must follow every read
     }
 }
@@ -708,25 +710,29 @@ hipError_t launch_s(int s, dim3 grid, dim3 block, hipStream_t st, A... args) {
     return hipGetLastError();
 }
 
-template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool FRC>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
 struct K55 {
     template <int S>
     struct at {
-        static constexpr auto fn = substep55_sweep<T, TW, TX, TY, S, PD, LD, FRC>;
+        static constexpr auto fn = substep55_sweep<T, TW, TX, TY, S, PD, LD, NT, FRC>;
     };
 };
-template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool FRC>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
+struct KRed {
+    static constexpr auto fn = substep55_sweep_red<T, TW, TX, TY, PD, LD, NT, FRC>;
+};
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
 struct K19 {
     template <int S>
     struct at {
-        static constexpr auto fn = substep19_pass1<T, TW, TX, TY, S, PD, LD, FRC>;
+        static constexpr auto fn = substep19_pass1<T, TW, TX, TY, S, PD, LD, NT, FRC>;
     };
 };
-template <typename T, typename TW, int TX, int TY, int PD, bool LD>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT>
 struct KBatch {
     template <int S>
     struct at {
-        static constexpr auto fn = substep55_batch<T, TW, TX, TY, S, PD, LD>;
+        static constexpr auto fn = substep55_batch<T, TW, TX, TY, S, PD, LD, NT>;
     };
 };
 template <typename T, typename TW, bool FRC>
@@ -757,26 +763,25 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
                 return launch_s<KDirect<T, TW, FRC>::template at>(s, grid, dim3(256), st, g, in,
                                                                   out, w, c, rk, fa);
             } else {
-                using K = K55<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>;
+                using K = K55<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, FRC>;
+                using KR = KRed<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, FRC>;
                 const int res = resident_blocks<K::template at<2>::fn>(k.tx * k.ty);
                 const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
                 // fuse only where the extra accumulators cost no occupancy
                 static const bool fuse_ok = [] {
                     int a = 0, b = 0;
                     const int blk = k.tx * k.ty;
-                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &a, substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>, blk,
-                            0) != hipSuccess ||
+                    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, KR::fn, blk, 0) !=
+                            hipSuccess ||
                         hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &b, substep55_sweep<T, TW, k.tx, k.ty, 3, k.pd, k.ld, FRC>, blk, 0) !=
-                            hipSuccess)
+                            &b, K::template at<3>::fn, blk, 0) != hipSuccess)
                         return false;
                     return a >= b && a > 0;
                 }();
                 if (s == 3 && partials && nparts && fuse_ok && sg.blocks <= part_cap) {
-                    hipLaunchKernelGGL((substep55_sweep_red<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>),
-                                       dim3(sg.blocks), dim3(k.tx * k.ty), 0, st, g, in, out, w,
-                                       c, rk, sg.ntx, sg.nty, sg.zlen, xcd_remap(), partials, fa);
+                    hipLaunchKernelGGL(KR::fn, dim3(sg.blocks), dim3(k.tx * k.ty), 0, st, g, in,
+                                       out, w, c, rk, sg.ntx, sg.nty, sg.zlen, xcd_remap(),
+                                       partials, fa);
                     *nparts = sg.blocks;
                     return hipGetLastError();
                 }
@@ -802,7 +807,7 @@ hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fi
             if constexpr (k.tx == 0) {
                 return hipErrorInvalidValue;
             } else {
-                using K = K19<T, TW, k.tx, k.ty, k.pd, k.ld, FRC>;
+                using K = K19<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, FRC>;
                 const int res = resident_blocks<K::template at<2>::fn>(k.tx * k.ty);
                 const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
                 return launch_s<K::template at>(s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in,
@@ -823,7 +828,7 @@ hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, 
         if constexpr (k.tx == 0) {
             return hipErrorInvalidValue;
         } else {
-            return launch_s<KBatch<T, TW, k.tx, k.ty, k.pd, k.ld>::template at>(
+            return launch_s<KBatch<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt>::template at>(
                 s, dim3(grid), dim3(k.tx * k.ty), st, boxes, items, nitems, parity, alpha, beta);
         }
     });
@@ -838,7 +843,7 @@ int batch55_blocks_per_cu(int tile) {
         } else {
             int n = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, substep55_batch<T, TW, k.tx, k.ty, 2, k.pd, k.ld>, k.tx * k.ty, 0) !=
+                    &n, substep55_batch<T, TW, k.tx, k.ty, 2, k.pd, k.ld, k.nt>, k.tx * k.ty, 0) !=
                 hipSuccess)
                 return 1;
             return n > 0 ? n : 1;
