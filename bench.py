@@ -6,8 +6,10 @@ box, FP32 storage and arithmetic, 55-point discretisation, fields lnrho and u
 as sums of 16 random-phase Fourier modes with |k| <= 16 and amplitude 0.1,
 nu = 1e-3, cs = 1, dt = 0.4 CFL, and FP64 global reductions (mass, kinetic
 energy, sum lnrho, max |u|, non-finite count) computed on the device after
-every step.  One step = 3 substeps, each a periodic ghost fill plus the
-fused right-hand-side + 2N-RK3 kernel, then the reductions.
+every step.  One step = 3 substeps, each one fused right-hand-side + 2N-RK3
+z-sweep kernel that resolves the periodic images in its loader; the third
+also produces the reductions' partials.  The state is stored as an array of
+structures (the four values of a point adjacent) unless --layout soa.
 
 Prints ONE JSON line (metric, value in grid-point updates/s, roofline of the
 dominant kernel measured with HIP events on its stream, the FP64 oracle's
@@ -35,7 +37,8 @@ ALG_BYTES = {("55p", "fp32"): 160, ("55p", "fp64"): 320, ("55p", "fp32_acc64"): 
              ("19p", "fp32"): 304, ("19p", "fp64"): 608}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_substep55_fp32_512.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1707_08900_amd", "csrc", f)
-               for f in ("sweep_common.hpp", "sweep_substep.hpp", "substep55_f32.hip")]
+               for f in ("sweep_common.hpp", "sweep_substep.hpp", "substep55_f32.hip",
+                         "substep55_aos_f32.hip")]
 
 
 def log(msg):
@@ -50,9 +53,9 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def load_traffic(shape):
+def load_traffic(shape, layout):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source with the same kernel shape and
+    taken on the current kernel source with the same layout, kernel shape and
     z-chunk length."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -63,11 +66,13 @@ def load_traffic(shape):
         return None
     if (t.get("tile"), t.get("zchunk")) != (shape.get("tile"), shape.get("zchunk")):
         return None
+    if t.get("layout", "soa") != layout:
+        return None
     return t.get("traffic_bytes_per_launch")
 
 
-def make_box(fd6, w, dev_fields, precision, variant, tune=True):
-    box = fd6.Box(w.shape, precision, variant)
+def make_box(fd6, w, dev_fields, precision, variant, tune=True, layout="soa"):
+    box = fd6.Box(w.shape, precision, variant, layout=layout)
     box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
     tuned = None
     if tune:
@@ -100,11 +105,11 @@ def timed_steps(torch, box, red, steps, warmup, timing=True):
     return wall, ev_ms, tm
 
 
-def sample_error(orc, fd6, si, w, dev_fields, precision, variant, nsamples=6):
+def sample_error(orc, fd6, si, w, dev_fields, precision, variant, nsamples=6, layout="soa"):
     """Max over sampled points of |gpu - oracle| / max|field| after one step
     from the workload's initial state (oracle on local patches)."""
     import numpy as np
-    box, _ = make_box(fd6, w, dev_fields, precision, variant, tune=False)
+    box, _ = make_box(fd6, w, dev_fields, precision, variant, tune=False, layout=layout)
     box.step(1)
     out = box.get_fields_device()
     box.close()
@@ -251,6 +256,8 @@ def main():
                     help="kernel shape of the headline run (skips the autotuner)")
     ap.add_argument("--zchunk", type=int, default=0,
                     help="z-chunk length with --tile (0: automatic)")
+    ap.add_argument("--layout", choices=("aos", "soa"), default="aos",
+                    help="device layout of the headline box's state")
     a = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -287,7 +294,8 @@ def main():
 
     dev_fields = [torch.from_numpy(f).cuda() for f in w.fields]
     red = torch.zeros(8, dtype=torch.float64, device="cuda")
-    box, tuned = make_box(fd6, w, dev_fields, "fp32", "55p", tune=a.tile is None)
+    box, tuned = make_box(fd6, w, dev_fields, "fp32", "55p", tune=a.tile is None,
+                          layout=a.layout)
     if a.tile is not None:
         box.set_tile(a.tile)
         box.set_zchunk(a.zchunk)
@@ -303,18 +311,18 @@ def main():
     box.close()
     ms_per_step = ev_ms / a.steps
     value = n ** 3 * a.steps / (ev_ms * 1e-3)
-    log(f"fp32 55p {n}^3: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} G updates/s "
+    log(f"fp32 55p {a.layout} {n}^3: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} G updates/s "
         f"(host wall {wall * 1e3 / a.steps:.3f} ms/step); mass {r[0]:.10e} ke {r[1]:.6e}")
 
     # dominant kernel: the fused 55-point substep kernel
     alg_per_launch = n ** 3 * ALG_BYTES[("55p", "fp32")] / 3.0
     avg_launch_s = kms * 1e-3 / klaunch
     achieved = alg_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic(tuned)
+    traffic = load_traffic(tuned, a.layout)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": "substep55_sweep (fused RHS + RK3)",
+                "kernel": f"substep55_sweep (fused RHS + RK3, {a.layout} layout)",
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": klaunch,
                 "alg_bytes_per_launch": alg_per_launch,
                 "ghost_fill_us_per_launch": round(gms * 1e3 / max(glaunch, 1), 2),
@@ -329,23 +337,29 @@ def main():
                            "ms_per_step": gev_ms / a.steps}
     log(f"fp32 55p {n}^3 graph replay: {gev_ms / a.steps:.3f} ms/step")
     if not a.no_check:
-        forms["fp32"]["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields, "fp32", "55p")
+        forms["fp32"]["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields,
+                                                             "fp32", "55p", layout=a.layout)
     if not a.no_forms:
         k2 = max(5, a.steps // 5)
-        for prec, var in (("fp64", "55p"), ("fp32_acc64", "55p"), ("fp32", "19p"),
-                          ("fp64", "19p")):
-            b2, tn = make_box(fd6, w, dev_fields, prec, var)
+        other = "soa" if a.layout == "aos" else "aos"
+        for prec, var, lay in (("fp64", "55p", "aos"), ("fp64", "55p", "soa"),
+                               ("fp32_acc64", "55p", "aos"), ("fp32", "55p", other),
+                               ("fp32", "19p", "soa"), ("fp64", "19p", "soa")):
+            b2, tn = make_box(fd6, w, dev_fields, prec, var, layout=lay)
             wl, em, tm = timed_steps(torch, b2, red, k2, 2)
             b2.close()
             v = n ** 3 * k2 / (em * 1e-3)
             entry = {"updates_per_s": v, "ms_per_step": em / k2,
                      "hbm_frac_step": v * ALG_BYTES[(var, prec)] / (HBM_PEAK_GBS * 1e9),
                      "speed_vs_fp64_55p": None}
+            entry["kernel_shape"] = {"tile": tn["tile"], "zchunk": tn["zchunk"]}
             if not a.no_check:
-                entry["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields, prec, var)
-            forms[f"{prec}_{var}"] = entry
-            log(f"{prec} {var}: {em / k2:.3f} ms/step, {v / 1e9:.2f} G updates/s")
-        base64 = forms["fp64_55p"]["updates_per_s"]
+                entry["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields, prec,
+                                                             var, layout=lay)
+            key = f"{prec}_{var}" + (f"_{lay}" if var == "55p" else "")
+            forms[key] = entry
+            log(f"{key}: {em / k2:.3f} ms/step, {v / 1e9:.2f} G updates/s")
+        base64 = forms["fp64_55p_aos"]["updates_per_s"]
         forms["fp32"]["speed_vs_fp64_55p"] = value / base64
         for k, e in forms.items():
             if k != "fp32":
@@ -362,8 +376,8 @@ def main():
         bf = forms["batched_fp32"]
         log(f"batched: {bf['ms_per_step']:.3f} ms/step, {bf['updates_per_s'] / 1e9:.2f} G updates/s "
             f"({bf['boxes']} boxes, {bf['points']} points, schedule {bf['schedule']})")
-        if "fp64_55p" in forms:
-            bf["speed_vs_fp64_55p"] = bf["updates_per_s"] / forms["fp64_55p"]["updates_per_s"]
+        if "fp64_55p_aos" in forms:
+            bf["speed_vs_fp64_55p"] = bf["updates_per_s"] / forms["fp64_55p_aos"]["updates_per_s"]
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -389,7 +403,7 @@ def main():
                                f"modes |k|<=16 A=0.1, nu=1e-3, cs=1, dt=0.4 CFL, FP64 reductions "
                                f"every step",
                    "grid": [n, n, n], "precision": "fp32", "variant": "55p",
-                   "kernel_shape": tuned},
+                   "layout": a.layout, "kernel_shape": tuned},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,

@@ -67,11 +67,23 @@ typedef enum { FD6_FP64 = 0, FD6_FP32 = 1, FD6_FP32_ACC64 = 2 } fd6_precision;
  * two pass (Sec. 4.2, Algorithm 3). */
 typedef enum { FD6_55P = 0, FD6_19P = 1 } fd6_variant;
 
+/* Device layout of the state and of the RK3 register (fd6_desc.flags).
+ * Default (0): one array per field.  FD6_LAYOUT_AOS: the four values of a grid
+ * point adjacent (array of structures, the alternative Sec. 7 proposes to
+ * save the partial memory segments of the x halos), so the sweep kernels move
+ * each point with 16-byte accesses.  Results are bit for bit those of the
+ * default layout.  The layout is internal: host and device field arrays at
+ * this boundary keep the compact per-field layout either way.  Supported for
+ * the 55-point method and the z-sweep shapes whose loader goes through
+ * registers (fd6_set_tile returns FD6_EUNSUPPORTED for the others); not for
+ * ensembles. */
+#define FD6_LAYOUT_AOS 1
+
 typedef struct {
     int32_t nx, ny, nz;  /* interior points, 6 <= n <= 4096 each */
     int32_t precision;   /* fd6_precision */
     int32_t variant;     /* fd6_variant */
-    int32_t flags;       /* reserved, must be 0 */
+    int32_t flags;       /* 0 or FD6_LAYOUT_AOS */
 } fd6_desc;
 
 /* Physical and numerical parameters: viscosity nu >= 0, sound speed cs >= 0,

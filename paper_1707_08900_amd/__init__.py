@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libfd6.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_acc64": 2}
 VARIANTS = {"55p": 0, "19p": 1}
+LAYOUTS = {"soa": 0, "aos": 1}  # fd6_desc.flags: 0, FD6_LAYOUT_AOS
 STATUS = {0: "FD6_OK", -1: "FD6_EINVAL", -2: "FD6_ESTATE", -3: "FD6_ENOMEM", -4: "FD6_EHIP",
           -5: "FD6_ENONFINITE", -6: "FD6_EUNSUPPORTED"}
 
@@ -131,9 +132,9 @@ def library():
     return _lib
 
 
-def workspace_bytes(shape, precision="fp32", variant="55p") -> int:
+def workspace_bytes(shape, precision="fp32", variant="55p", layout="soa") -> int:
     nz, ny, nx = shape
-    d = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS[variant], 0)
+    d = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS[variant], LAYOUTS[layout])
     out = ctypes.c_size_t()
     rc = library().fd6_workspace_bytes(ctypes.byref(d), ctypes.byref(out))
     if rc != 0:
@@ -146,19 +147,23 @@ def _dptr(a: np.ndarray):
 
 
 class Box:
-    """One periodic box: lnrho, ux, uy, uz of shape (nz, ny, nx) on the GPU."""
+    """One periodic box: lnrho, ux, uy, uz of shape (nz, ny, nx) on the GPU.
+
+    layout: device layout of the state, "soa" (one array per field) or "aos"
+    (the four values of a point adjacent; 55-point method only)."""
 
     def __init__(self, shape: Sequence[int], precision: str = "fp32", variant: str = "55p",
-                 device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+                 device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None,
+                 layout: str = "soa"):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1707_08900_amd needs a ROCm GPU (gfx950); none is visible")
         self.lib = library()
         self.shape = tuple(int(s) for s in shape)
-        self.precision, self.variant = precision, variant
+        self.precision, self.variant, self.layout = precision, variant, layout
         self.device = torch.device(device)
         nz, ny, nx = self.shape
-        self.desc = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS[variant], 0)
-        nbytes = workspace_bytes(self.shape, precision, variant)
+        self.desc = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS[variant], LAYOUTS[layout])
+        nbytes = workspace_bytes(self.shape, precision, variant, layout)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         aligned = (base + 255) // 256 * 256

@@ -15,6 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfd6.so")
 SOURCES = ["aux_kernels.hip", "substep55_f32.hip", "substep55_f64.hip", "substep55_f32w64.hip",
+           "substep55_aos_f32.hip", "substep55_aos_f64.hip", "substep55_aos_f32w64.hip",
            "substep19.hip", "fd6_abi.cpp"]
 
 ARCH = "gfx950"

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void import_kernel(Geom g, const double* __res
         int i = (int)(e - r * g.nx);
         int j = (int)(r % g.ny);
         long long k = zbeg + r / g.ny;
-        dst[g.origin + k * g.plane + (long long)j * g.px + i] = (T)src[e];
+        dst[(g.origin + k * g.plane + (long long)j * g.px + i) * g.vs] = (T)src[e];
     }
 }
 
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void export_kernel(Geom g, const T* __restrict
         int i = (int)(e - r * g.nx);
         int j = (int)(r % g.ny);
         long long k = zbeg + r / g.ny;
-        dst[e] = (double)src[g.origin + k * g.plane + (long long)j * g.px + i];
+        dst[e] = (double)src[(g.origin + k * g.plane + (long long)j * g.px + i) * g.vs];
     }
 }
 
@@ -92,15 +92,15 @@ __global__ __launch_bounds__(256) void export_w_kernel(Geom g, const TW* __restr
         int i = (int)(e - r * g.nx);
         int j = (int)(r % g.ny);
         long long k = r / g.ny;
-        dst[e] = (double)src[k * g.wplane + (long long)j * g.wpx + i];
+        dst[e] = (double)src[(k * g.wplane + (long long)j * g.wpx + i) * g.vs];
     }
 }
 
 template <typename TW>
-__global__ __launch_bounds__(256) void zero_w_kernel(Fields4<TW> w, long long n) {
+__global__ __launch_bounds__(256) void zero_w_kernel(Fields4<TW> w, long long n, int vs) {
     const long long e0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     for (long long e = e0; e < n; e += (long long)gridDim.x * blockDim.x)
-        for (int q = 0; q < 4; ++q) w.f[q][e] = TW(0);
+        for (int q = 0; q < 4; ++q) w.f[q][e * vs] = TW(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(Geom g, Fi
         const int k = r / g.ny, j = r - k * g.ny;
         const long long base = g.origin + (long long)k * g.plane + (long long)j * g.px;
         for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
-            const long long c = base + i;
+            const long long c = (base + i) * g.vs;
             const double lr = (double)f.f[0][c], ux = (double)f.f[1][c], uy = (double)f.f[2][c],
                          uz = (double)f.f[3][c];
             const double rho = exp(lr);
@@ -205,6 +205,7 @@ unsigned grid_for(long long n, int threads, int maxblocks = 65536) {
 
 template <typename T>
 hipError_t launch_ghost_fill(const Geom& g, Fields4<T> f, int nfields, hipStream_t s) {
+    if (g.vs != 1) return hipErrorInvalidValue;  // only the sweep shapes take other layouts
     const long long wx = g.nx + 2 * kR, wy = g.ny + 2 * kR;
     const long long nzc = 2LL * kR * wy * wx;
     const long long nyc = (long long)g.nz * 2 * kR * wx;
@@ -244,7 +245,7 @@ hipError_t launch_export_w(const Geom& g, const TW* src, double* dst, hipStream_
 template <typename TW>
 hipError_t launch_zero_w(const Geom& g, Fields4<TW> w, hipStream_t s) {
     hipLaunchKernelGGL(zero_w_kernel<TW>, dim3(grid_for(g.wfelems, 256)), dim3(256), 0, s, w,
-                       g.wfelems);
+                       g.wfelems, g.vs);
     return hipGetLastError();
 }
 

@@ -156,10 +156,11 @@ int validate_desc(const fd6_desc* d) {
     if (!d) return FD6_EINVAL;
     if (d->nx < 2 * kR || d->ny < 2 * kR || d->nz < 2 * kR) return FD6_EINVAL;
     if (d->nx > 4096 || d->ny > 4096 || d->nz > 4096) return FD6_EINVAL;
-    if (d->flags != 0) return FD6_EINVAL;
+    if (d->flags != 0 && d->flags != FD6_LAYOUT_AOS) return FD6_EINVAL;
     if (d->variant != FD6_55P && d->variant != FD6_19P) return FD6_EINVAL;
     size_t a, b;
     if (precision_sizes(d->precision, &a, &b)) return FD6_EINVAL;
+    if (d->flags == FD6_LAYOUT_AOS && d->variant != FD6_55P) return FD6_EUNSUPPORTED;
     return FD6_OK;
 }
 
@@ -183,17 +184,20 @@ int make_plan(const fd6_desc* d, Plan* p) {
     g.wfelems = (long long)round_up((size_t)(g.wplane * d->nz) * p->wsize, kAlign) /
                 (long long)p->wsize;
     if (g.felems > kMaxFieldElems || g.wfelems > kMaxFieldElems) return FD6_EUNSUPPORTED;
+    // array of structures: one array of 4 values per point, field q starting
+    // q elements in (the same bytes as four separate fields)
+    const bool aos = d->flags == FD6_LAYOUT_AOS;
+    g.vs = aos ? 4 : 1;
     size_t off = 0;
     const size_t fbytes = (size_t)g.felems * p->tsize;
+    const size_t wbytes = (size_t)g.wfelems * p->wsize;
     for (int s = 0; s < 2; ++s)
-        for (int q = 0; q < 4; ++q) {
-            p->off_state[s][q] = off;
-            off += fbytes;
-        }
-    for (int q = 0; q < 4; ++q) {
-        p->off_w[q] = off;
-        off += (size_t)g.wfelems * p->wsize;
-    }
+        for (int q = 0; q < 4; ++q)
+            p->off_state[s][q] =
+                aos ? off + 4 * s * fbytes + q * p->tsize : off + (4 * s + q) * fbytes;
+    off += 8 * fbytes;
+    for (int q = 0; q < 4; ++q) p->off_w[q] = aos ? off + q * p->wsize : off + q * wbytes;
+    off += 4 * wbytes;
     p->off_div = off;
     if (d->variant == FD6_19P) off += fbytes;
     p->off_partials = off;
@@ -337,9 +341,10 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
     const ForceArgs<T>* frc = b->force_on ? &fa : nullptr;
     if (b->desc.variant == FD6_55P) {
         double* parts = (red_out && s == 3) ? b->partials : nullptr;
+        auto launch = g.vs == 4 ? launch_substep55_aos<T, TW> : launch_substep55<T, TW>;
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_substep55<T, TW>(g, in, out, w, c, rk, s, b->tile, b->zchunk, parts,
-                                               kFusedPartials, &nparts, frc, b->stream)));
+            HIPCHK(b, launch(g, in, out, w, c, rk, s, b->tile, b->zchunk, parts, kFusedPartials,
+                             &nparts, frc, b->stream));
             return FD6_OK;
         });
         if (rc) return rc;
@@ -655,7 +660,7 @@ int make_batch_plan(int n, const fd6_desc* d, BatchPlan* bp) {
         int rc = make_plan(&d[i], &bp->box[i]);
         if (rc) return rc;
         if (d[i].precision != d[0].precision) return FD6_EINVAL;
-        if (d[i].variant != FD6_55P) return FD6_EUNSUPPORTED;
+        if (d[i].variant != FD6_55P || d[i].flags != 0) return FD6_EUNSUPPORTED;
         bp->base[i] = off;
         // this box's state and w fields (the per-box plan puts them first)
         off += bp->box[i].off_div;
@@ -1132,6 +1137,7 @@ const char* fd6_last_error(const fd6_box* b) { return b ? b->err.c_str() : ""; }
 // one-thread-per-point kernel, 1.. = z-sweep tile shapes).
 int fd6_set_tile(fd6_box* b, int32_t tile) {
     if (!b || tile < 0 || tile >= substep55_tile_count()) return FD6_EINVAL;
+    if (b->geom.vs == 4 && !substep55_aos_tile_ok(tile)) return FD6_EUNSUPPORTED;
     if (tile != b->tile) b->drop_graphs();
     b->tile = tile;
     return FD6_OK;

@@ -31,6 +31,11 @@ struct Geom {
     int wpx;               // elements per w row
     long long wplane;      // wpx * ny
     long long wfelems;     // elements per w field (multiple of 256 B)
+    // Values per grid point in memory: 1 = one array per field; 4 = the four
+    // fields of a point adjacent (array of structures).  Element indices above
+    // count points; field q of point e is at f[q][e * vs], with f[q] = f[0] + q
+    // when vs = 4 (the same holds for w).
+    int vs = 1;
 };
 
 // Four state fields (lnrho, ux, uy, uz) and four w fields.
@@ -128,6 +133,16 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
                             const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
                             double* partials, int part_cap, int* nparts,
                             const ForceArgs<T>* frc, hipStream_t st);
+// The same substep for the array-of-structures layout (vs = 4): each loaded
+// or stored point is one 16-byte (FP32) or two 16-byte (FP64) accesses
+// instead of one access per field.  Register-loader z-sweep shapes only
+// (substep55_aos_tile_ok).
+template <typename T, typename TW>
+hipError_t launch_substep55_aos(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                                const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                                int zchunk, double* partials, int part_cap, int* nparts,
+                                const ForceArgs<T>* frc, hipStream_t st);
+bool substep55_aos_tile_ok(int tile);
 // Whether a kernel shape reads the ghost zone of its input (the z-sweep
 // shapes resolve the periodic images in their loader instead).
 bool substep55_reads_ghosts(int tile);

@@ -46,6 +46,46 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsig
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, CP);
 }
 
+// One grid point of the array-of-structures layout: the four fields in 16
+// (FP32) or 32 (FP64) consecutive bytes, moved with 16-byte accesses.
+// (Whole vectors are bit-cast: with this compiler a bit cast of a single
+// element of the loaded vector shrank the access to one dword and gave wrong
+// values for the other elements.)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int CP = 0>
+__device__ __forceinline__ void bload_point(float (&v)[4], __amdgpu_buffer_rsrc_t r,
+                                            unsigned off) {
+    const f32x4 a = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = a[i];
+}
+template <int CP = 0>
+__device__ __forceinline__ void bload_point(double (&v)[4], __amdgpu_buffer_rsrc_t r,
+                                            unsigned off) {
+    // a dropped point (off = kDropOffset) stays beyond the range at off + 16
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CP);
+    const u32x4 b = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, CP);
+    v[0] = __builtin_bit_cast(double, u32x2{a[0], a[1]});
+    v[1] = __builtin_bit_cast(double, u32x2{a[2], a[3]});
+    v[2] = __builtin_bit_cast(double, u32x2{b[0], b[1]});
+    v[3] = __builtin_bit_cast(double, u32x2{b[2], b[3]});
+}
+template <int CP = 0>
+__device__ __forceinline__ void bstore_point(const float (&v)[4], __amdgpu_buffer_rsrc_t r,
+                                             unsigned off) {
+    const f32x4 a{v[0], v[1], v[2], v[3]};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, a), r, off, 0, CP);
+}
+template <int CP = 0>
+__device__ __forceinline__ void bstore_point(const double (&v)[4], __amdgpu_buffer_rsrc_t r,
+                                             unsigned off) {
+    const u32x2 p0 = __builtin_bit_cast(u32x2, v[0]), p1 = __builtin_bit_cast(u32x2, v[1]);
+    const u32x2 p2 = __builtin_bit_cast(u32x2, v[2]), p3 = __builtin_bit_cast(u32x2, v[3]);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{p0[0], p0[1], p1[0], p1[1]}, r, off, 0, CP);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{p2[0], p2[1], p3[0], p3[1]}, r, off + 16u, 0, CP);
+}
+
 // LD = false: the next plane is loaded into registers and written to LDS by
 // the threads; LD = true: it is copied by the buffer unit straight into LDS
 // (64 consecutive dwords per wave instruction), with no staging registers.
@@ -106,18 +146,22 @@ struct SweepCtx {
 // its periodic image, so the sweep kernels neither read nor need the ghost
 // zone.  Cells beyond x < nx + 3, y < ny + 3 never feed a stored point and are
 // dropped.
-template <typename T, typename TW, int TX, int TY, bool LD>
+// VS: values per point in memory (1, or 4 for the array-of-structures
+// layout); all byte offsets and plane sizes scale with it.
+template <typename T, typename TW, int TX, int TY, bool LD, int VS = 1>
 __device__ __forceinline__ void sweep_ctx_init(SweepCtx<T, TX, TY, LD>& X, const Geom& g, int x0,
                                                int y0) {
     using Sh = SweepShape<T, TX, TY, LD>;
+    static_assert(VS == 1 || !LD, "the LDS-copy loader reads one array per field");
+    constexpr int PT = VS * (int)sizeof(T), PW = VS * (int)sizeof(TW);  // bytes per point
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    X.plane_bytes = (unsigned)(g.plane * (long long)sizeof(T));
-    X.wplane_bytes = (unsigned)(g.wplane * (long long)sizeof(TW));
+    X.plane_bytes = (unsigned)(g.plane * (long long)PT);
+    X.wplane_bytes = (unsigned)(g.wplane * (long long)PW);
     auto wrapped_off = [&](int gx, int gy) -> unsigned {  // gx, gy in [-3, ...)
         if (gx >= g.nx + kR || gy >= g.ny + kR) return kDropOffset;
         const int ix = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
         const int iy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-        return (unsigned)(((iy + kR) * g.px + (ix + kR)) * (int)sizeof(T));
+        return (unsigned)(((iy + kR) * g.px + (ix + kR)) * PT);
     };
     if constexpr (LD) {
         // dword d = 64 j + lane of the padded plane tile, j = wave + js NW
@@ -152,8 +196,8 @@ __device__ __forceinline__ void sweep_ctx_init(SweepCtx<T, TX, TY, LD>& X, const
     }
     const int xo = x0 + tx, yo = y0 + ty;
     const bool store = xo < g.nx && yo < g.ny;
-    X.lane_o = store ? (unsigned)(((yo + kR) * g.px + (xo + kR)) * (int)sizeof(T)) : kDropOffset;
-    X.lane_w = store ? (unsigned)((yo * g.wpx + xo) * (int)sizeof(TW)) : kDropOffset;
+    X.lane_o = store ? (unsigned)(((yo + kR) * g.px + (xo + kR)) * PT) : kDropOffset;
+    X.lane_w = store ? (unsigned)((yo * g.wpx + xo) * PW) : kDropOffset;
 }
 
 // Workgroup index -> (tile x, tile y, z chunk): consecutive tiles (x fastest,

@@ -176,28 +176,42 @@ struct SweepRegs {
 
 // Loads plane `corner` of the four fields (this thread's cells) into
 // register set RS; bytes = 0 loads nothing.
-template <int RS, typename T, typename TW, int TX, int TY, int NH>
+template <int RS, int VS, typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_prefetch(SweepRegs<T, TW, NH>& R,
                                                const SweepCtx<T, TX, TY>& X,
                                                const Fields4<T>& in, long long corner,
                                                unsigned bytes) {
+    if constexpr (VS == 4) {
+        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[0] + 4 * corner, bytes);
+        bload_point(R.pf[RS], rs, X.goff_int);
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, bytes);
-        R.pf[RS][f] = bload((T*)nullptr, rs, X.goff_int);
+        for (int h = 0; h < NH; ++h) bload_point(R.ph[RS][h], rs, X.goff_h[h]);
+    } else {
 #pragma unroll
-        for (int h = 0; h < NH; ++h) R.ph[RS][h][f] = bload((T*)nullptr, rs, X.goff_h[h]);
+        for (int f = 0; f < 4; ++f) {
+            const __amdgpu_buffer_rsrc_t rs = plane_rsrc(in.f[f] + corner, bytes);
+            R.pf[RS][f] = bload((T*)nullptr, rs, X.goff_int);
+#pragma unroll
+            for (int h = 0; h < NH; ++h) R.ph[RS][h][f] = bload((T*)nullptr, rs, X.goff_h[h]);
+        }
     }
 }
 
-template <int RS, bool NT, typename T, typename TW, int NH>
+template <int RS, bool NT, int VS, typename T, typename TW, int NH>
 __device__ __forceinline__ void load_w(SweepRegs<T, TW, NH>& R, const Fields4<TW>& w,
                                        const Geom& g, int o, unsigned wplane_bytes,
                                        unsigned lane_w) {
+    constexpr int CP = NT ? kNonTemporal : 0;
+    if constexpr (VS == 4) {
+        bload_point<CP>(R.wq[RS], plane_rsrc(w.f[0] + 4 * (long long)o * g.wplane, wplane_bytes),
+                        lane_w);
+    } else {
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-        R.wq[RS][f] = bload<NT ? kNonTemporal : 0>((TW*)nullptr,
-                            plane_rsrc(w.f[f] + (long long)o * g.wplane, wplane_bytes), lane_w);
+        for (int f = 0; f < 4; ++f)
+            R.wq[RS][f] = bload<CP>((TW*)nullptr,
+                                    plane_rsrc(w.f[f] + (long long)o * g.wplane, wplane_bytes),
+                                    lane_w);
+    }
 }
 
 // LD: copy plane `corner` of the four fields into one LDS buffer.  Chunk j
@@ -224,9 +238,8 @@ __device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
     }
 }
 
-template <int PH, int S, int PD, bool LD, bool NT, bool P19, bool RED, bool FRC, typename T,
-          typename TW,
-          int TX, int TY, int NH>
+template <int PH, int S, int PD, bool LD, bool NT, int VS, bool P19, bool RED, bool FRC,
+          typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, TW, NH>& R,
                                            const SweepCtx<T, TX, TY, LD>& X, T* lds,
                                            lds_t<T> lds3, const Geom& g, const Fields4<T>& in,
@@ -254,9 +267,9 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         if constexpr (S != 1) {
             if constexpr (PD >= 2) {
                 const bool next_out = t + 1 >= 2 * kR && t + 1 < nplanes;
-                load_w<(PH + 1) & 1, NT>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u, X.lane_w);
+                load_w<(PH + 1) & 1, NT, VS>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u, X.lane_w);
             } else {
-                load_w<0, NT>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
+                load_w<0, NT, VS>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
             }
         }
         // prefetched plane p -> LDS buffer (PH & 1)
@@ -267,8 +280,8 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             for (int h = 0; h < NH; ++h) buf[f * Sh::FS + X.loff_h[h]] = R.ph[RS][h][f];
         }
         // plane p + PD -> the register set just emptied
-        sweep_prefetch<RS>(R, X, in, plane_corner(g, p + PD),
-                           t + PD < nplanes ? X.plane_bytes : 0u);
+        sweep_prefetch<RS, VS>(R, X, in, plane_corner(g, p + PD),
+                               t + PD < nplanes ? X.plane_bytes : 0u);
         __syncthreads();
     } else {
         // this wave's copies of plane p are complete before the barrier; after
@@ -278,7 +291,7 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         sweep_dma<T, TX, TY>(X, in, plane_corner(g, p + 1), lds3 + ((PH + 1) & 1) * 4 * Sh::FS,
                              t + 1 < nplanes ? X.plane_bytes : 0u);
         if constexpr (S != 1) {
-            load_w<0, NT>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
+            load_w<0, NT, VS>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
         }
     }
 
@@ -365,16 +378,26 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         }
         // ghost corner (-3, -3) of output plane o
         const long long ocorner = g.origin + (long long)o * g.plane - kR * g.px - kR;
+        constexpr int CP = NT ? kNonTemporal : 0;
         T vout[4];
+        TW wout[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
             TW wv = S == 1 ? TW(0) : R.wq[WS][f];
             const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv, rk);
             vout[f] = v;
-            bstore<NT ? kNonTemporal : 0>(v, plane_rsrc(out.f[f] + ocorner, ob), X.lane_o);
+            wout[f] = wv;
+            if constexpr (VS == 1) {
+                bstore<CP>(v, plane_rsrc(out.f[f] + ocorner, ob), X.lane_o);
+                if constexpr (S != 3)
+                    bstore<CP>(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, wb), X.lane_w);
+            }
+        }
+        if constexpr (VS == 4) {
+            bstore_point<CP>(vout, plane_rsrc(out.f[0] + 4 * ocorner, ob), X.lane_o);
             if constexpr (S != 3)
-                bstore<NT ? kNonTemporal : 0>(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, wb),
-                                              X.lane_w);
+                bstore_point<CP>(wout, plane_rsrc(w.f[0] + 4 * (long long)o * g.wplane, wb),
+                                 X.lane_w);
         }
         // 19-point pass 1 also stores the divergence for pass 2
         if constexpr (P19)
@@ -554,7 +577,7 @@ __device__ __forceinline__ void red_store_n(double v[5], double* part) {
 
 // RED: also reduce the FP64 diagnostics of the output and store this
 // workgroup's partial at part[blockIdx.x * kReduceSlots ...].
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT,
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS,
           bool P19 = false, bool RED = false, bool FRC = false>
 __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
@@ -565,7 +588,8 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
     using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int NH = Sh::NH;
     SweepCtx<T, TX, TY, LD> X;
-    sweep_ctx_init<T, TW, TX, TY, LD>(X, g, x0, y0);
+    static_assert(VS == 1 || !P19, "the 19-point passes use one array per field");
+    sweep_ctx_init<T, TW, TX, TY, LD, VS>(X, g, x0, y0);
 
     SweepRegs<T, TW, NH> R;
 #pragma unroll
@@ -597,37 +621,38 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
     if constexpr (LD) {
         sweep_dma<T, TX, TY>(X, in, plane_corner(g, zb - kR), lds3, X.plane_bytes);
     } else {
-        sweep_prefetch<0>(R, X, in, plane_corner(g, zb - kR), X.plane_bytes);
+        sweep_prefetch<0, VS>(R, X, in, plane_corner(g, zb - kR), X.plane_bytes);
         if constexpr (PD >= 2)
-            sweep_prefetch<1>(R, X, in, plane_corner(g, zb - kR + 1), X.plane_bytes);
+            sweep_prefetch<1, VS>(R, X, in, plane_corner(g, zb - kR + 1), X.plane_bytes);
         if constexpr (PD == 4) {
             // a chunk sweeps at least 7 planes, so these exist
-            sweep_prefetch<2>(R, X, in, plane_corner(g, zb - kR + 2), X.plane_bytes);
-            sweep_prefetch<3>(R, X, in, plane_corner(g, zb - kR + 3), X.plane_bytes);
+            sweep_prefetch<2, VS>(R, X, in, plane_corner(g, zb - kR + 2), X.plane_bytes);
+            sweep_prefetch<3, VS>(R, X, in, plane_corner(g, zb - kR + 3), X.plane_bytes);
         }
     }
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        sweep_step<0, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
-        sweep_step<1, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
-        sweep_step<2, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
-        sweep_step<3, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
-        sweep_step<4, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
-        sweep_step<5, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
-        sweep_step<6, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
-        sweep_step<7, S, PD, LD, NT, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in, out, w,
-                                                  dv, cf, rk, fa.tab);
+        sweep_step<0, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<1, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<2, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<3, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<4, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<5, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<6, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<7, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
+                                                      out, w, dv, cf, rk, fa.tab);
     }
     if constexpr (RED) red_store_n<SweepShape<T, TX, TY, LD>::NW>(R.red, part);
 }
 
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, bool FRC>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS,
+          bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
                      RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, ForceArgs<T> fa) {
@@ -635,13 +660,13 @@ void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
     if (t.zb >= t.ze) return;
-    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, false, false, FRC>(
+    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, VS, false, false, FRC>(
         g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
 }
 
 // Substep 3 with the FP64 diagnostics of the new state fused in: one partial
 // per workgroup (every workgroup of the grid has a non-empty chunk).
-template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, int VS, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
                          RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, double* part,
@@ -649,7 +674,7 @@ void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, C
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
-    sweep_tile<T, TW, TX, TY, 3, PD, LD, NT, false, true, FRC>(
+    sweep_tile<T, TW, TX, TY, 3, PD, LD, NT, VS, false, true, FRC>(
         g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, part, fa);
 }
 
@@ -664,7 +689,7 @@ void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv
     __shared__ T lds[2 * 4 * Sh::FS];
     const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
     if (t.zb >= t.ze) return;
-    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, true, false, FRC>(
+    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, 1, true, false, FRC>(
         g, in, out, w, dv, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
 }
 
@@ -693,7 +718,7 @@ void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
         const Fields4<T> in = bx->st[parity], out = bx->st[parity ^ 1];
         const Fields4<TW> w = bx->w;
         const RKCoef<TW> rk{alpha, beta, bx->dt};
-        sweep_tile<T, TW, TX, TY, S, PD, LD, NT>(g, in, out, w, nullptr, cf, rk, wi.x0, wi.y0,
+        sweep_tile<T, TW, TX, TY, S, PD, LD, NT, 1>(g, in, out, w, nullptr, cf, rk, wi.x0, wi.y0,
                                              wi.zb, wi.ze, lds, (lds_t<T>)lds);
         __syncthreads();  // the next item's first LDS write must follow every read
     }
@@ -710,16 +735,16 @@ hipError_t launch_s(int s, dim3 grid, dim3 block, hipStream_t st, A... args) {
     return hipGetLastError();
 }
 
-template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, int VS, bool FRC>
 struct K55 {
     template <int S>
     struct at {
-        static constexpr auto fn = substep55_sweep<T, TW, TX, TY, S, PD, LD, NT, FRC>;
+        static constexpr auto fn = substep55_sweep<T, TW, TX, TY, S, PD, LD, NT, VS, FRC>;
     };
 };
-template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, int VS, bool FRC>
 struct KRed {
-    static constexpr auto fn = substep55_sweep_red<T, TW, TX, TY, PD, LD, NT, FRC>;
+    static constexpr auto fn = substep55_sweep_red<T, TW, TX, TY, PD, LD, NT, VS, FRC>;
 };
 template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, bool FRC>
 struct K19 {
@@ -743,28 +768,30 @@ struct KDirect {
     };
 };
 
-}  // namespace
-
-
-template <typename T, typename TW>
-hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
-                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                            double* partials, int part_cap, int* nparts,
-                            const ForceArgs<T>* frc, hipStream_t st) {
+// VS = 1: one array per field; VS = 4: array of structures (register-loader
+// z-sweep shapes only).
+template <typename T, typename TW, int VS>
+hipError_t launch_substep55_vs(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                               const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                               int zchunk, double* partials, int part_cap, int* nparts,
+                               const ForceArgs<T>* frc, hipStream_t st) {
     if (nparts) *nparts = 0;
+    if (g.vs != VS) return hipErrorInvalidValue;
     const ForceArgs<T> fa = frc ? *frc : ForceArgs<T>{nullptr, nullptr};
     auto go = [&](auto force) -> hipError_t {
         constexpr bool FRC = decltype(force)::value;
         return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
             constexpr TileCfg k = kTiles[decltype(I)::value];
-            if constexpr (k.tx == 0) {
+            if constexpr (VS != 1 && (k.tx == 0 || k.ld)) {
+                return hipErrorInvalidValue;
+            } else if constexpr (k.tx == 0) {
                 const dim3 grid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + 3) / 4),
                                 (unsigned)g.nz);
                 return launch_s<KDirect<T, TW, FRC>::template at>(s, grid, dim3(256), st, g, in,
                                                                   out, w, c, rk, fa);
             } else {
-                using K = K55<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, FRC>;
-                using KR = KRed<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, FRC>;
+                using K = K55<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, VS, FRC>;
+                using KR = KRed<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, VS, FRC>;
                 const int res = resident_blocks<K::template at<2>::fn>(k.tx * k.ty);
                 const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
                 // fuse only where the extra accumulators cost no occupancy
@@ -792,6 +819,26 @@ hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields
         });
     };
     return frc ? go(std::true_type{}) : go(std::false_type{});
+}
+
+}  // namespace
+
+template <typename T, typename TW>
+hipError_t launch_substep55(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                            const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
+                            double* partials, int part_cap, int* nparts,
+                            const ForceArgs<T>* frc, hipStream_t st) {
+    return launch_substep55_vs<T, TW, 1>(g, in, out, w, c, rk, s, tile, zchunk, partials,
+                                         part_cap, nparts, frc, st);
+}
+
+template <typename T, typename TW>
+hipError_t launch_substep55_aos(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                                const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
+                                int zchunk, double* partials, int part_cap, int* nparts,
+                                const ForceArgs<T>* frc, hipStream_t st) {
+    return launch_substep55_vs<T, TW, 4>(g, in, out, w, c, rk, s, tile, zchunk, partials,
+                                         part_cap, nparts, frc, st);
 }
 
 // Pass 1 of the 19-point method in a z-sweep shape (tile >= 1).

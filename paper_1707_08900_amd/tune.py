@@ -3,7 +3,7 @@
 Times every kernel shape the library offers (fd6_tile_count) on the caller's
 own box with HIP events, then a few z-chunk lengths for the fastest shape,
 keeps the fastest pair, and caches the choice in a JSON
-file keyed by grid shape, precision, variant and device name (path from
+file keyed by grid shape, precision, variant, layout and device name (path from
 FD6_TUNE_CACHE, default ~/.cache/fd6_tune.json).  Tuning runs real steps, so
 it advances the box's state: call it before init_fields of the actual run,
 or re-initialise afterwards.
@@ -16,7 +16,9 @@ from typing import Dict, Optional
 
 import torch
 
-from . import Box, tile_count
+from . import Box, Fd6Error, tile_count
+
+FD6_EUNSUPPORTED = -6
 
 
 def _cache_path() -> str:
@@ -27,7 +29,7 @@ def _cache_path() -> str:
 def _key(box: Box) -> str:
     name = torch.cuda.get_device_name(box.device)
     nz, ny, nx = box.shape
-    return f"{name}|{nx}x{ny}x{nz}|{box.precision}|{box.variant}"
+    return f"{name}|{nx}x{ny}x{nz}|{box.precision}|{box.variant}|{box.layout}"
 
 
 def _load() -> Dict[str, dict]:
@@ -74,7 +76,13 @@ def tune(box: Box, steps: int = 3, use_cache: bool = True,
         return cache[key]
     box.set_zchunk(0)
     tiles = candidates if candidates is not None else list(range(1, tile_count()))
-    timings = {t: time_tile(box, t, steps, reduce) for t in tiles}
+    timings = {}
+    for t in tiles:
+        try:
+            timings[t] = time_tile(box, t, steps, reduce)
+        except Fd6Error as e:  # a shape the box's layout does not take
+            if e.status != FD6_EUNSUPPORTED:
+                raise
     best = min(timings, key=timings.get)
     box.set_tile(best)
     nz = box.shape[0]

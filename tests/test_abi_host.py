@@ -55,10 +55,27 @@ def test_workspace_bytes_validation(pkg):
     assert lib.fd6_workspace_bytes(ctypes.byref(desc(prec=0)), ctypes.byref(out)) == 0
     assert out.value > fp32  # FP64 needs more
     for bad in (desc(nx=5), desc(ny=0), desc(nz=4097), desc(prec=3), desc(var=2),
-                desc(flags=1)):
+                desc(flags=2), desc(flags=-1)):
         assert lib.fd6_workspace_bytes(ctypes.byref(bad), ctypes.byref(out)) == -1
     assert lib.fd6_workspace_bytes(None, ctypes.byref(out)) == -1
     assert lib.fd6_workspace_bytes(ctypes.byref(desc()), None) == -1
+
+
+def test_aos_layout_flag(pkg):
+    """FD6_LAYOUT_AOS: same workspace as one array per field, 55-point only."""
+    lib = pkg.library()
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    for prec in (0, 1, 2):
+        assert lib.fd6_workspace_bytes(ctypes.byref(desc(prec=prec)), ctypes.byref(a)) == 0
+        assert lib.fd6_workspace_bytes(ctypes.byref(desc(prec=prec, flags=1)),
+                                       ctypes.byref(b)) == 0
+        assert a.value == b.value
+    assert lib.fd6_workspace_bytes(ctypes.byref(desc(var=1, flags=1)), ctypes.byref(a)) == -6
+    assert pkg.workspace_bytes((20, 24, 28), "fp64", "55p", "aos") == \
+        pkg.workspace_bytes((20, 24, 28), "fp64", "55p")
+    # ensembles take the default layout only
+    ds = (pkg.Fd6Desc * 2)(desc(), desc(flags=1))
+    assert lib.fd6_batch_workspace_bytes(2, ds, ctypes.byref(a)) == -6
 
 
 def test_workspace_grows_with_19p_div_field(pkg):

@@ -1,0 +1,164 @@
+"""GPU: the array-of-structures state layout (the alternative storage of the
+discussion in Sec. 7), selected by FD6_LAYOUT_AOS.
+
+Only the device layout changes, and every point goes through the same
+arithmetic, so an AoS box reproduces the default layout bit for bit (state,
+right-hand side, fused and standalone diagnostics, forced steps, graph
+replays); against the FP64 oracle it meets the parity tolerances of one step
+(FP64 1e-12, FP32 1e-5).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthetic_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+EUNSUPPORTED = -6
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "fp32_acc64": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def fd6():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible ROCm GPU")
+    import paper_1707_08900_amd as p
+    return p
+
+
+def aos_tiles(fd6):
+    return [t for t in range(1, fd6.tile_count()) if t != 9]
+
+
+def make(fd6, w, precision, layout, tile=None, zchunk=None):
+    box = fd6.Box(w.shape, precision, "55p", layout=layout)
+    if tile is not None:
+        box.set_tile(tile)
+    if zchunk is not None:
+        box.set_zchunk(zchunk)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(w.fields)
+    return box
+
+
+def rel_err(a, b):
+    return max(float(np.max(np.abs(x - y)) / max(np.max(np.abs(y)), 1e-300)) for x, y in zip(a, b))
+
+
+def test_unsupported_forms_are_refused(fd6):
+    box = fd6.Box((16, 16, 16), "fp32", "55p", layout="aos")
+    for t in (0, 9):  # the direct kernels read ghost zones; shape 9 copies planes into LDS
+        with pytest.raises(fd6.Fd6Error) as e:
+            box.set_tile(t)
+        assert e.value.status == EUNSUPPORTED
+    box.set_tile(6)
+    box.close()
+    with pytest.raises(fd6.Fd6Error) as e:
+        fd6.Box((16, 16, 16), "fp32", "19p", layout="aos")
+    assert e.value.status == EUNSUPPORTED
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_acc64"])
+def test_aos_matches_default_layout_bitwise(fd6, precision):
+    """Ragged box (no dimension a multiple of a tile), every shape, 2 steps."""
+    w = si.noise_box((21, 19, 70), seed=12)
+    ref = make(fd6, w, precision, "soa", tile=6)
+    ref.step(2)
+    want = ref.get_fields()
+    ref.close()
+    for t in aos_tiles(fd6):
+        box = make(fd6, w, precision, "aos", tile=t)
+        box.step(2)
+        got = box.get_fields()
+        box.close()
+        print(f"aos {precision} tile {t}", flush=True)
+        for q in range(4):
+            assert np.array_equal(got[q], want[q]), (t, q)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_aos_one_step_parity_with_oracle(fd6, orc, precision):
+    w = si.small_parity_box(seed=5)
+    base = si.as_float32_exact(w.fields) if precision == "fp32" else w.fields
+    ref = orc.rk3(base, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1)
+    box = make(fd6, w, precision, "aos")
+    box.step(1)
+    err = rel_err(box.get_fields(), ref)
+    box.close()
+    print(f"aos {precision} 32^3: rel err {err:.3e}", flush=True)
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_aos_rhs_and_diagnostics_match(fd6, precision):
+    import torch
+    w = si.noise_box((33, 40, 24), seed=4)
+    boxes = {lay: make(fd6, w, precision, lay, tile=2, zchunk=9) for lay in ("soa", "aos")}
+    r = {lay: b.rhs() for lay, b in boxes.items()}
+    for q in range(4):
+        assert np.array_equal(r["aos"][q], r["soa"][q])
+    red = {}
+    for lay, b in boxes.items():
+        b.init_fields(w.fields)
+        out = torch.zeros(8, dtype=torch.float64, device=b.device)
+        b.step_reduce(2, out)  # fused diagnostics in substep 3
+        red[lay] = (out.cpu().numpy()[:5], b.reduce())  # and the standalone pass
+    assert np.array_equal(red["aos"][0], red["soa"][0])
+    assert red["aos"][1] == red["soa"][1]
+    f = {lay: b.get_fields() for lay, b in boxes.items()}
+    for q in range(4):
+        assert np.array_equal(f["aos"][q], f["soa"][q])
+    for b in boxes.values():
+        b.close()
+
+
+def test_aos_forced_and_graph_steps_match(fd6):
+    w = si.noise_box((24, 30, 36), seed=8)
+    draws = si.forcing_draws(4, 1.0, 2.0, 0.05, seed=2)
+    res = {}
+    for lay in ("soa", "aos"):
+        for graph in (False, True):
+            b = make(fd6, w, "fp32", lay, tile=12)
+            b.set_graph(graph)
+            for d in draws:
+                b.set_forcing(d)
+                b.step(1)
+            res[(lay, graph)] = b.get_fields()
+            b.close()
+    want = res[("soa", False)]
+    for key, got in res.items():
+        for q in range(4):
+            assert np.array_equal(got[q], want[q]), key
+
+
+def test_aos_sound_wave_stays_on_the_closed_form(fd6):
+    """A linear sound wave along x for 200 steps in the AoS layout: phase and
+    amplitude of the discrete dispersion relation of the sixth-order D1 with
+    RK3, as for the default layout."""
+    # amplitude small enough that the quadratic terms (relative size ~ amp k t)
+    # stay far below the tolerance
+    n, k, amp, nu = 64, 3, 1e-8, 0.0
+    h = 2 * math.pi / n
+    x = np.arange(n) * h
+    lnrho = np.broadcast_to(amp * np.sin(k * x), (n, n, n)).copy()
+    zero = np.zeros((n, n, n))
+    dt = 0.4 * h
+    box = fd6.Box((n, n, n), "fp64", "55p", layout="aos")
+    box.set_params(nu, 1.0, h, h, h, dt)
+    box.init_fields([lnrho, zero, zero, zero])
+    nsteps = 200
+    box.step(nsteps)
+    lr = box.get_fields()[0][0, 0, :]
+    box.close()
+    # discrete wave number of D1 (eqs. first_derivatives) and the RK3 growth
+    th = k * h
+    kd = (45 * math.sin(th) - 9 * math.sin(2 * th) + math.sin(3 * th)) / (30 * h)
+    z = 1j * kd * dt  # eigenvalues +-i kd cs of the linear system
+    g = 1 + z + z * z / 2 + z ** 3 / 6
+    t_phase = nsteps * np.angle(g)
+    a = abs(g) ** nsteps
+    pred = amp * a * np.cos(t_phase) * np.sin(k * x)  # standing wave from rest
+    assert np.max(np.abs(lr - pred)) <= 1e-5 * amp
