@@ -126,7 +126,7 @@ def sample_error(orc, fd6, si, w, dev_fields, precision, variant, nsamples=6, la
     return worst
 
 
-def batch_form(torch, fd6, si, steps):
+def batch_form(torch, fd6, si, steps, layout="aos"):
     """64 independent boxes (edges from {32, 48, 64, 96}, per-box nu and
     amplitude, FP32), one persistent launch per substep, graph per step.
     The kernel shape and z-chunk are tuned on the ensemble itself."""
@@ -134,7 +134,7 @@ def batch_form(torch, fd6, si, steps):
     members = si.ensemble(64)
     ws = [m.workload for m in members]
     pts = sum(int(np.prod(w.shape)) for w in ws)
-    b = fd6.Batch([w.shape for w in ws], "fp32")
+    b = fd6.Batch([w.shape for w in ws], "fp32", layout=layout)
     b.set_params([(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt) for w in ws])
 
     def reinit():
@@ -372,12 +372,15 @@ def main():
             f"{ff['unforced_ms_per_step']:.3f} ms/step unforced")
 
     if not a.no_batch:
-        forms["batched_fp32"] = batch_form(torch, fd6, si, max(10, a.steps // 2))
-        bf = forms["batched_fp32"]
-        log(f"batched: {bf['ms_per_step']:.3f} ms/step, {bf['updates_per_s'] / 1e9:.2f} G updates/s "
-            f"({bf['boxes']} boxes, {bf['points']} points, schedule {bf['schedule']})")
-        if "fp64_55p_aos" in forms:
-            bf["speed_vs_fp64_55p"] = bf["updates_per_s"] / forms["fp64_55p_aos"]["updates_per_s"]
+        for lay, key in (("aos", "batched_fp32"), ("soa", "batched_fp32_soa")):
+            forms[key] = batch_form(torch, fd6, si, max(10, a.steps // 2), layout=lay)
+            bf = forms[key]
+            log(f"batched {lay}: {bf['ms_per_step']:.3f} ms/step, "
+                f"{bf['updates_per_s'] / 1e9:.2f} G updates/s ({bf['boxes']} boxes, "
+                f"{bf['points']} points, schedule {bf['schedule']})")
+            if "fp64_55p_aos" in forms:
+                bf["speed_vs_fp64_55p"] = (bf["updates_per_s"] /
+                                           forms["fp64_55p_aos"]["updates_per_s"])
 
     cpu = None
     if not a.no_cpu_baseline:

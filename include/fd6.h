@@ -75,8 +75,8 @@ typedef enum { FD6_55P = 0, FD6_19P = 1 } fd6_variant;
  * default layout.  The layout is internal: host and device field arrays at
  * this boundary keep the compact per-field layout either way.  Supported for
  * the 55-point method and the z-sweep shapes whose loader goes through
- * registers (fd6_set_tile returns FD6_EUNSUPPORTED for the others); not for
- * ensembles. */
+ * registers (fd6_set_tile and fd6_batch_set_schedule return FD6_EUNSUPPORTED
+ * for the others); an ensemble takes one layout for all its boxes. */
 #define FD6_LAYOUT_AOS 1
 
 typedef struct {
@@ -249,8 +249,8 @@ const char *fd6_last_error(const fd6_box *box);
  * ------------------------------------------------------------------------- */
 typedef struct fd6_batch fd6_batch;
 
-/* Workspace for n boxes described by descs[0..n-1] (same precision; variant
- * FD6_55P, else FD6_EUNSUPPORTED). */
+/* Workspace for n boxes described by descs[0..n-1] (same precision and the
+ * same flags, else FD6_EINVAL; variant FD6_55P, else FD6_EUNSUPPORTED). */
 int fd6_batch_workspace_bytes(int32_t n, const fd6_desc *descs, size_t *bytes);
 
 /* Create the ensemble in the caller's workspace (256-byte aligned). */

@@ -297,20 +297,21 @@ class Box:
 
 class Batch:
     """An ensemble of independent periodic boxes advanced together on the GPU
-    (one persistent launch per substep, a captured graph per step)."""
+    (one persistent launch per substep, a captured graph per step); layout as
+    for Box, one for every box."""
 
     def __init__(self, shapes, precision: str = "fp32", device: str = "cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, layout: str = "soa"):
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1707_08900_amd needs a ROCm GPU (gfx950); none is visible")
         self.lib = library()
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.n = len(self.shapes)
-        self.precision = precision
+        self.precision, self.layout = precision, layout
         self.device = torch.device(device)
         arr = (Fd6Desc * self.n)()
         for i, (nz, ny, nx) in enumerate(self.shapes):
-            arr[i] = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS["55p"], 0)
+            arr[i] = Fd6Desc(nx, ny, nz, PRECISIONS[precision], VARIANTS["55p"], LAYOUTS[layout])
         self._descs = arr
         need = ctypes.c_size_t()
         rc = self.lib.fd6_batch_workspace_bytes(self.n, arr, ctypes.byref(need))

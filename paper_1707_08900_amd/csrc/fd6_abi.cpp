@@ -87,6 +87,7 @@ struct fd6_batch {
     int precision = 0;
     int tile = 4;  // 32 x 8 z-sweep
     int zchunk = 0;  // 0: whole box per work item
+    bool aos = false;  // every box in the array-of-structures layout
     bool use_graph = true;
     hipStream_t stream = nullptr;   // caller's stream (graph launches, transfers)
     hipStream_t cap = nullptr;      // private stream used only for graph capture
@@ -660,7 +661,8 @@ int make_batch_plan(int n, const fd6_desc* d, BatchPlan* bp) {
         int rc = make_plan(&d[i], &bp->box[i]);
         if (rc) return rc;
         if (d[i].precision != d[0].precision) return FD6_EINVAL;
-        if (d[i].variant != FD6_55P || d[i].flags != 0) return FD6_EUNSUPPORTED;
+        if (d[i].variant != FD6_55P) return FD6_EUNSUPPORTED;
+        if (d[i].flags != d[0].flags) return FD6_EINVAL;  // one layout per ensemble
         bp->base[i] = off;
         // this box's state and w fields (the per-box plan puts them first)
         off += bp->box[i].off_div;
@@ -738,7 +740,9 @@ int build_items(fd6_batch* b) {
     int dev = 0, cus = 0;
     HIPCHK(b, hipGetDevice(&dev));
     HIPCHK(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    long long gsz = (long long)cus * batch55_blocks_per_cu<T, TW>(b->tile);
+    const int per_cu = b->aos ? batch55_blocks_per_cu_aos<T, TW>(b->tile)
+                              : batch55_blocks_per_cu<T, TW>(b->tile);
+    long long gsz = (long long)cus * per_cu;
     gsz = std::min<long long>(gsz, b->nitems);
     if (gsz >= 8) gsz = gsz / 8 * 8;
     b->grid = (int)std::max<long long>(gsz, 1);
@@ -748,10 +752,11 @@ int build_items(fd6_batch* b) {
 
 template <typename T, typename TW>
 int batch_substeps(fd6_batch* b, hipStream_t st, int parity) {
+    auto launch = b->aos ? launch_batch55_aos<T, TW> : launch_batch55<T, TW>;
     for (int s = 0; s < 3; ++s) {
-        HIPCHK(b, (launch_batch55<T, TW>(static_cast<const BatchBox<T, TW>*>(b->boxes_dev),
-                                         b->items_dev, b->nitems, b->grid, parity, s + 1,
-                                         b->tile, TW(kAlpha[s]), TW(kBeta[s]), st)));
+        HIPCHK(b, launch(static_cast<const BatchBox<T, TW>*>(b->boxes_dev), b->items_dev,
+                         b->nitems, b->grid, parity, s + 1, b->tile, TW(kAlpha[s]),
+                         TW(kBeta[s]), st));
         parity ^= 1;
     }
     return FD6_OK;
@@ -1180,6 +1185,7 @@ int fd6_batch_create(int32_t n, const fd6_desc* descs, void* d_ws, size_t bytes,
         fd6_batch* b = new fd6_batch();
         b->n = n;
         b->precision = descs[0].precision;
+        b->aos = descs[0].flags == FD6_LAYOUT_AOS;
         b->stream = static_cast<hipStream_t>(stream);
         b->ws = static_cast<char*>(d_ws);
         b->ws_bytes = bytes;
@@ -1260,6 +1266,7 @@ int fd6_batch_init_fields(fd6_batch* b, int32_t box, const double* lnrho, const 
 int fd6_batch_set_schedule(fd6_batch* b, int32_t tile, int32_t zchunk) {
     int tx, ty;
     if (!b || zchunk < 0 || substep55_tile_dims(tile, &tx, &ty)) return FD6_EINVAL;
+    if (b->aos && !substep55_aos_tile_ok(tile)) return FD6_EUNSUPPORTED;
     return guarded(b, [&]() -> int {
         b->tile = tile;
         b->zchunk = zchunk;

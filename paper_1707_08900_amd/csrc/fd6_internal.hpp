@@ -168,6 +168,13 @@ hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, 
                           hipStream_t st);
 template <typename T, typename TW>
 int batch55_blocks_per_cu(int tile);
+// The same for ensembles whose boxes all use the array-of-structures layout.
+template <typename T, typename TW>
+hipError_t launch_batch55_aos(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                              int grid, int parity, int s, int tile, TW alpha, TW beta,
+                              hipStream_t st);
+template <typename T, typename TW>
+int batch55_blocks_per_cu_aos(int tile);
 
 // 19-point method: pass 1 (divergence, partial update) and pass 2 (the
 // (nu/3) grad div u term).  tile 0 runs the direct kernels, which read the

@@ -700,7 +700,7 @@ void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv
 // that XCD's L2.  Per-box geometry, pointers, coefficients and time step come
 // from device memory, so a captured graph never needs re-capture when they
 // change.  Per point the arithmetic is the single-box kernel's.
-template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT>
+template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS>
 __global__ __launch_bounds__(TX* TY)
 void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
                      const BatchItem* __restrict__ items, int nitems, int parity, TW alpha,
@@ -718,7 +718,7 @@ void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
         const Fields4<T> in = bx->st[parity], out = bx->st[parity ^ 1];
         const Fields4<TW> w = bx->w;
         const RKCoef<TW> rk{alpha, beta, bx->dt};
-        sweep_tile<T, TW, TX, TY, S, PD, LD, NT, 1>(g, in, out, w, nullptr, cf, rk, wi.x0, wi.y0,
+        sweep_tile<T, TW, TX, TY, S, PD, LD, NT, VS>(g, in, out, w, nullptr, cf, rk, wi.x0, wi.y0,
                                              wi.zb, wi.ze, lds, (lds_t<T>)lds);
         __syncthreads();  // the next item's first LDS write must follow every read
     }
@@ -753,11 +753,11 @@ struct K19 {
         static constexpr auto fn = substep19_pass1<T, TW, TX, TY, S, PD, LD, NT, FRC>;
     };
 };
-template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT>
+template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, int VS>
 struct KBatch {
     template <int S>
     struct at {
-        static constexpr auto fn = substep55_batch<T, TW, TX, TY, S, PD, LD, NT>;
+        static constexpr auto fn = substep55_batch<T, TW, TX, TY, S, PD, LD, NT, VS>;
     };
 };
 template <typename T, typename TW, bool FRC>
@@ -866,36 +866,66 @@ hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fi
     return frc ? go(std::true_type{}) : go(std::false_type{});
 }
 
-template <typename T, typename TW>
-hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
-                          int grid, int parity, int s, int tile, TW alpha, TW beta,
-                          hipStream_t st) {
+namespace {
+
+template <typename T, typename TW, int VS>
+hipError_t launch_batch55_vs(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                             int grid, int parity, int s, int tile, TW alpha, TW beta,
+                             hipStream_t st) {
     return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
         constexpr TileCfg k = kTiles[decltype(I)::value];
-        if constexpr (k.tx == 0) {
+        if constexpr (k.tx == 0 || (VS != 1 && k.ld)) {
             return hipErrorInvalidValue;
         } else {
-            return launch_s<KBatch<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt>::template at>(
+            return launch_s<KBatch<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, VS>::template at>(
                 s, dim3(grid), dim3(k.tx * k.ty), st, boxes, items, nitems, parity, alpha, beta);
         }
     });
 }
 
-template <typename T, typename TW>
-int batch55_blocks_per_cu(int tile) {
+template <typename T, typename TW, int VS>
+int batch55_blocks_per_cu_vs(int tile) {
     return with_tile(tile, 1, [&](auto I) -> int {
         constexpr TileCfg k = kTiles[decltype(I)::value];
-        if constexpr (k.tx == 0) {
+        if constexpr (k.tx == 0 || (VS != 1 && k.ld)) {
             return 1;
         } else {
             int n = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &n, substep55_batch<T, TW, k.tx, k.ty, 2, k.pd, k.ld, k.nt>, k.tx * k.ty, 0) !=
-                hipSuccess)
+                    &n, substep55_batch<T, TW, k.tx, k.ty, 2, k.pd, k.ld, k.nt, VS>, k.tx * k.ty,
+                    0) != hipSuccess)
                 return 1;
             return n > 0 ? n : 1;
         }
     });
+}
+
+}  // namespace
+
+template <typename T, typename TW>
+hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                          int grid, int parity, int s, int tile, TW alpha, TW beta,
+                          hipStream_t st) {
+    return launch_batch55_vs<T, TW, 1>(boxes, items, nitems, grid, parity, s, tile, alpha, beta,
+                                       st);
+}
+
+template <typename T, typename TW>
+hipError_t launch_batch55_aos(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
+                              int grid, int parity, int s, int tile, TW alpha, TW beta,
+                              hipStream_t st) {
+    return launch_batch55_vs<T, TW, 4>(boxes, items, nitems, grid, parity, s, tile, alpha, beta,
+                                       st);
+}
+
+template <typename T, typename TW>
+int batch55_blocks_per_cu(int tile) {
+    return batch55_blocks_per_cu_vs<T, TW, 1>(tile);
+}
+
+template <typename T, typename TW>
+int batch55_blocks_per_cu_aos(int tile) {
+    return batch55_blocks_per_cu_vs<T, TW, 4>(tile);
 }
 
 }  // namespace fd6

@@ -73,9 +73,14 @@ def test_aos_layout_flag(pkg):
     assert lib.fd6_workspace_bytes(ctypes.byref(desc(var=1, flags=1)), ctypes.byref(a)) == -6
     assert pkg.workspace_bytes((20, 24, 28), "fp64", "55p", "aos") == \
         pkg.workspace_bytes((20, 24, 28), "fp64", "55p")
-    # ensembles take the default layout only
+    # an ensemble takes one layout for all its boxes
     ds = (pkg.Fd6Desc * 2)(desc(), desc(flags=1))
-    assert lib.fd6_batch_workspace_bytes(2, ds, ctypes.byref(a)) == -6
+    assert lib.fd6_batch_workspace_bytes(2, ds, ctypes.byref(a)) == -1
+    ds = (pkg.Fd6Desc * 2)(desc(flags=1), desc(nx=48, flags=1))
+    assert lib.fd6_batch_workspace_bytes(2, ds, ctypes.byref(a)) == 0
+    ds0 = (pkg.Fd6Desc * 2)(desc(), desc(nx=48))
+    assert lib.fd6_batch_workspace_bytes(2, ds0, ctypes.byref(b)) == 0
+    assert a.value == b.value
 
 
 def test_workspace_grows_with_19p_div_field(pkg):
