@@ -6,11 +6,13 @@
 namespace fd6 {
 
 template hipError_t launch_substep55_aos<float, float>(const Geom&, Fields4<float>, Fields4<float>,
-                                                  Fields4<float>, const Coef<float>&,
-                                                  const RKCoef<float>&, int, int, int, double*,
-                                                  int, int*, const ForceArgs<float>*, hipStream_t);
-template hipError_t launch_batch55_aos<float, float>(const BatchBox<float, float>*, const BatchItem*,
-                                                  int, int, int, int, int, float, float, hipStream_t);
+                                                   Fields4<float>, const Coef<float>&,
+                                                   const RKCoef<float>&, int, int, int, double*,
+                                                   int, int*, const ForceArgs<float>*,
+                                                   hipStream_t);
+template hipError_t launch_batch55_aos<float, float>(const BatchBox<float, float>*,
+                                                 const BatchItem*, int, int, int, int, int,
+                                                 float, float, hipStream_t);
 template int batch55_blocks_per_cu_aos<float, float>(int);
 
 bool substep55_aos_tile_ok(int tile) {

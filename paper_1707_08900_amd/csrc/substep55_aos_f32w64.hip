@@ -6,11 +6,13 @@
 namespace fd6 {
 
 template hipError_t launch_substep55_aos<float, double>(const Geom&, Fields4<float>, Fields4<float>,
-                                                  Fields4<double>, const Coef<float>&,
-                                                  const RKCoef<double>&, int, int, int, double*,
-                                                  int, int*, const ForceArgs<float>*, hipStream_t);
-template hipError_t launch_batch55_aos<float, double>(const BatchBox<float, double>*, const BatchItem*,
-                                                  int, int, int, int, int, double, double, hipStream_t);
+                                                   Fields4<double>, const Coef<float>&,
+                                                   const RKCoef<double>&, int, int, int, double*,
+                                                   int, int*, const ForceArgs<float>*,
+                                                   hipStream_t);
+template hipError_t launch_batch55_aos<float, double>(const BatchBox<float, double>*,
+                                                 const BatchItem*, int, int, int, int, int,
+                                                 double, double, hipStream_t);
 template int batch55_blocks_per_cu_aos<float, double>(int);
 
 }  // namespace fd6

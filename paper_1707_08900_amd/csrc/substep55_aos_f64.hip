@@ -6,11 +6,13 @@
 namespace fd6 {
 
 template hipError_t launch_substep55_aos<double, double>(const Geom&, Fields4<double>, Fields4<double>,
-                                                  Fields4<double>, const Coef<double>&,
-                                                  const RKCoef<double>&, int, int, int, double*,
-                                                  int, int*, const ForceArgs<double>*, hipStream_t);
-template hipError_t launch_batch55_aos<double, double>(const BatchBox<double, double>*, const BatchItem*,
-                                                  int, int, int, int, int, double, double, hipStream_t);
+                                                   Fields4<double>, const Coef<double>&,
+                                                   const RKCoef<double>&, int, int, int, double*,
+                                                   int, int*, const ForceArgs<double>*,
+                                                   hipStream_t);
+template hipError_t launch_batch55_aos<double, double>(const BatchBox<double, double>*,
+                                                 const BatchItem*, int, int, int, int, int,
+                                                 double, double, hipStream_t);
 template int batch55_blocks_per_cu_aos<double, double>(int);
 
 }  // namespace fd6

@@ -267,7 +267,8 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         if constexpr (S != 1) {
             if constexpr (PD >= 2) {
                 const bool next_out = t + 1 >= 2 * kR && t + 1 < nplanes;
-                load_w<(PH + 1) & 1, NT, VS>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u, X.lane_w);
+                load_w<(PH + 1) & 1, NT, VS>(R, w, g, o + 1, next_out ? X.wplane_bytes : 0u,
+                                             X.lane_w);
             } else {
                 load_w<0, NT, VS>(R, w, g, o, outstep ? X.wplane_bytes : 0u, X.lane_w);
             }

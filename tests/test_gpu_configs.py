@@ -3,8 +3,10 @@
 * 128^3, 16 random-phase modes |k| <= 8, A = 1e-2, nu = 2e-3, 100 RK3 steps:
   the full fields against the FP64 oracle, both discretisations.
 * 512^3 (and 256^3) single box, FP32, |k| <= 16, A = 0.1, nu = 1e-3: one step
-  in the benchmark's kernel shape, sampled points against the oracle's local
-  patch update (a point after one step depends only on a 19^3 neighbourhood).
+  in the benchmark's launch configuration (tuned shape, fused diagnostics;
+  both layouts at 512^3), sampled points against the oracle's local patch
+  update (a point after one step depends only on a 19^3 neighbourhood), and
+  the fused diagnostics against the oracle's reductions.
 * 768^3 linear sound wave lnrho = 1e-4 sin(4x), u = 0, nu = 1e-4, 1000 steps:
   the x-profile equals the oracle's exact 768 x 8 x 8 slab replica (the field
   never varies in y and z), every column is identical, the wave follows the
@@ -83,18 +85,24 @@ def test_55p_and_19p_differ_only_slightly(fd6, mid):
         assert 0 < diff < 1e-2 * change, (q, diff, change)
 
 
-@pytest.mark.parametrize("n", [256, 512])
-def test_large_box_sampled_points(fd6, orc, n):
+@pytest.mark.parametrize("n,layout", [(256, "soa"), (512, "soa"), (512, "aos")])
+def test_large_box_sampled_points(fd6, orc, n, layout):
+    """The benchmark's launch configuration: shape and z-chunk tuned on
+    reducing steps, one step through rk3_step_reduce (diagnostics fused into
+    substep 3).  Sampled points against the oracle's patch update; the fused
+    diagnostics against the oracle's reductions of the exported state."""
     import torch
     w = si.large_box(n)
-    box = fd6.Box(w.shape, "fp32")
+    box = fd6.Box(w.shape, "fp32", layout=layout)
     from paper_1707_08900_amd import tune
     box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
     dev = [torch.from_numpy(f).cuda() for f in w.fields]
     box.init_fields(dev)
-    tune.tune(box, steps=1, use_cache=False)
+    shape = tune.tune(box, steps=1, use_cache=False, reduce=True)
+    print(f"{n}^3 {layout}: shape {shape['tile']}, zchunk {shape['zchunk']}", flush=True)
     box.init_fields(dev)
-    box.step(1)
+    red = torch.zeros(8, dtype=torch.float64, device="cuda")
+    box.step_reduce(1, red)
     out = box.get_fields_device()
     inp = si.as_float32_exact(w.fields)
     scale = [float(np.max(np.abs(f))) for f in inp]
@@ -106,8 +114,20 @@ def test_large_box_sampled_points(fd6, orc, n):
         ref = orc.rk3_point(inp, c, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1)
         for q in range(4):
             worst = max(worst, abs(float(out[q][c].item()) - ref[q]) / scale[q])
-    print(f"{n}^3 fp32 sampled rel err {worst:.3e}", flush=True)
+    print(f"{n}^3 fp32 {layout} sampled rel err {worst:.3e}", flush=True)
     assert worst <= 1e-5
+    # diagnostics of the stored FP32 state: FP64 sums in a different order
+    got = red.cpu().numpy()
+    host = [t.cpu().numpy() for t in out]
+    del out
+    want = orc.reduce(host, w.dx, w.dy, w.dz)
+    npts = float(n) ** 3
+    assert got[0] == pytest.approx(want["mass"], rel=1e-12)
+    assert got[1] == pytest.approx(want["kinetic_energy"], rel=1e-12)
+    assert abs(got[2] - want["sum_lnrho"]) <= 1e-12 * npts * max(abs(f).max() for f in host[:1])
+    assert got[3] == pytest.approx(want["umax"], rel=1e-14)  # |u|^2 may be fused-multiply-added
+    assert got[4] == 0 and want["nonfinite"] == 0
+    box.close()
 
 
 def sound_closed_form(k, h, cs, nu, dt, nsteps, A):
