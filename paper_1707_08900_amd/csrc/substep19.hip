@@ -204,12 +204,11 @@ template <typename T, typename TW, int TX, int TY, int S, bool NT>
 __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __restrict__ dv,
                                                           Fields4<T> out, Fields4<TW> w,
                                                           Coef<T> cf, RKCoef<TW> rk, TW cgd,
-                                                          int ntx, int nty, int zlen,
-                                                          int remap) {
+                                                          SweepGrid m) {
     using Sh = SweepShape<T, TX, TY>;
     constexpr int NH = Sh::NH;
     __shared__ T lds[2 * Sh::FS];
-    const TileXY tl = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    const TileXY tl = sweep_tile_of(g, TX, TY, m);
     if (tl.zb >= tl.ze) return;
     SweepCtx<T, TX, TY> X;
     sweep_ctx_init<T, TW, TX, TY, false>(X, g, tl.tx, tl.ty);
@@ -278,19 +277,18 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
                 resident_blocks<substep19_pass2<T, TW, k.tx, k.ty, 2, k.nt>>(k.tx * k.ty);
             const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
             const dim3 grid(sg.blocks), block(k.tx * k.ty);
-            const int rm = xcd_remap();
             switch (s) {
             case 1:
                 hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 1, k.nt>), grid, block, 0,
-                                   st, g, div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                                   st, g, div, out, w, c, rk, cgd, sg);
                 break;
             case 2:
                 hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 2, k.nt>), grid, block, 0,
-                                   st, g, div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                                   st, g, div, out, w, c, rk, cgd, sg);
                 break;
             default:
                 hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 3, k.nt>), grid, block, 0,
-                                   st, g, div, out, w, c, rk, cgd, sg.ntx, sg.nty, sg.zlen, rm);
+                                   st, g, div, out, w, c, rk, cgd, sg);
                 break;
             }
         }

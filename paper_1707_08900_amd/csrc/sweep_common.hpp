@@ -200,11 +200,38 @@ __device__ __forceinline__ void sweep_ctx_init(SweepCtx<T, TX, TY, LD>& X, const
     X.lane_w = store ? (unsigned)((yo * g.wpx + xo) * PW) : kDropOffset;
 }
 
-// Workgroup index -> (tile x, tile y, z chunk): consecutive tiles (x fastest,
-// then y, then chunk) go to one XCD, which receives every 8th workgroup.
+// Workgroup index -> (tile x, tile y, z chunk).  Each XCD receives every 8th
+// workgroup; with remap the grid is renumbered so that one XCD takes a
+// contiguous range of tiles instead.  Within a z chunk the tiles are ordered
+// in column blocks gx tiles wide (x fastest inside a block, then y, then the
+// next block), so the tiles an XCD holds at once cover a near-square region
+// and the halo rows and columns they read from outside it (from HBM rather
+// than from that XCD's L2) are few.  gx >= ntx is plain row order.
 struct SweepGrid {
     int ntx, nty, zlen, blocks;
+    int gx;     // column-block width in tiles
+    int remap;  // 1: contiguous tile ranges per XCD
 };
+
+// Column-block width that minimises the halo fraction of the region one XCD
+// holds at once (per_xcd tiles of tx x ty; a region spanning a whole
+// periodic axis reads no halo along it).  FD6_SWEEP_GX > 0 overrides it.
+inline int sweep_block_width(int ntx, int nty, int tx, int ty, int per_xcd) {
+    static const int forced = [] {
+        const char* e = getenv("FD6_SWEEP_GX");
+        return e ? atoi(e) : 0;
+    }();
+    if (forced > 0) return forced < ntx ? forced : ntx;
+    int best = ntx;
+    double best_cost = 1e30;
+    for (int gx = ntx; gx >= 1; --gx) {
+        const int rows = (per_xcd + gx - 1) / gx;
+        const double xh = gx >= ntx ? 0.0 : 2.0 * kR / (gx * tx);
+        const double yh = rows >= nty ? 0.0 : 2.0 * kR / ((double)rows * ty);
+        if (xh + yh < best_cost - 1e-12) best_cost = xh + yh, best = gx;
+    }
+    return best;
+}
 
 // zchunk > 0 fixes the chunk length (planes); 0 chooses it.  resident: how
 // many workgroups of the kernel the device holds at once.  The automatic
@@ -231,6 +258,9 @@ inline SweepGrid sweep_grid(const Geom& g, int tx, int ty, int zchunk, int resid
     s.zlen = (g.nz + nch - 1) / nch;
     nch = (g.nz + s.zlen - 1) / s.zlen;
     s.blocks = (int)(tiles * nch);
+    s.remap = xcd_remap();
+    s.gx = s.remap ? sweep_block_width(s.ntx, s.nty, tx, ty, resident > 8 ? resident / 8 : 1)
+                   : s.ntx;
     return s;
 }
 
@@ -256,16 +286,22 @@ struct TileXY {
     int tx, ty, zb, ze;
 };
 
-__device__ __forceinline__ TileXY sweep_tile_of(const Geom& g, int TX, int TY, int ntx, int nty,
-                                                int zlen, int remap) {
+__device__ __forceinline__ TileXY sweep_tile_of(const Geom& g, int TX, int TY,
+                                                const SweepGrid& m) {
     int b = blockIdx.x;
     const int nb = gridDim.x;
-    if (remap && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int tix = b % ntx;
-    const int tiy = (b / ntx) % nty;
-    const int ch = b / (ntx * nty);
-    const int zb = ch * zlen;
-    return TileXY{tix * TX, tiy * TY, zb, min(zb + zlen, g.nz)};
+    if (m.remap && (nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int per = m.ntx * m.nty;
+    const int ch = b / per;
+    int l = b - ch * per;                     // tile within the chunk
+    const int blk = l / (m.gx * m.nty);       // column block
+    const int bx0 = blk * m.gx;
+    const int bw = min(m.gx, m.ntx - bx0);    // the last block may be narrower
+    l -= blk * m.gx * m.nty;
+    const int tiy = l / bw;
+    const int tix = bx0 + (l - tiy * bw);
+    const int zb = ch * m.zlen;
+    return TileXY{tix * TX, tiy * TY, zb, min(zb + m.zlen, g.nz)};
 }
 
 // Kernel shapes of the z-sweep substeps.  Index 0 is the direct kernel (one

@@ -656,10 +656,10 @@ template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool 
           bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
-                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, ForceArgs<T> fa) {
+                     RKCoef<TW> rk, SweepGrid m, ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
-    const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    const TileXY t = sweep_tile_of(g, TX, TY, m);
     if (t.zb >= t.ze) return;
     sweep_tile<T, TW, TX, TY, S, PD, LD, NT, VS, false, false, FRC>(
         g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
@@ -670,11 +670,11 @@ void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<
 template <typename T, typename TW, int TX, int TY, int PD, bool LD, bool NT, int VS, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
-                         RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, double* part,
+                         RKCoef<TW> rk, SweepGrid m, double* part,
                          ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
-    const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    const TileXY t = sweep_tile_of(g, TX, TY, m);
     sweep_tile<T, TW, TX, TY, 3, PD, LD, NT, VS, false, true, FRC>(
         g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, part, fa);
 }
@@ -685,10 +685,10 @@ void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, C
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, bool FRC>
 __global__ __launch_bounds__(TX* TY)
 void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv, Coef<T> cf,
-                     RKCoef<TW> rk, int ntx, int nty, int zlen, int remap, ForceArgs<T> fa) {
+                     RKCoef<TW> rk, SweepGrid m, ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
-    const TileXY t = sweep_tile_of(g, TX, TY, ntx, nty, zlen, remap);
+    const TileXY t = sweep_tile_of(g, TX, TY, m);
     if (t.zb >= t.ze) return;
     sweep_tile<T, TW, TX, TY, S, PD, LD, NT, 1, true, false, FRC>(
         g, in, out, w, dv, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
@@ -808,14 +808,12 @@ hipError_t launch_substep55_vs(const Geom& g, Fields4<T> in, Fields4<T> out, Fie
                 }();
                 if (s == 3 && partials && nparts && fuse_ok && sg.blocks <= part_cap) {
                     hipLaunchKernelGGL(KR::fn, dim3(sg.blocks), dim3(k.tx * k.ty), 0, st, g, in,
-                                       out, w, c, rk, sg.ntx, sg.nty, sg.zlen, xcd_remap(),
-                                       partials, fa);
+                                       out, w, c, rk, sg, partials, fa);
                     *nparts = sg.blocks;
                     return hipGetLastError();
                 }
                 return launch_s<K::template at>(s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in,
-                                                out, w, c, rk, sg.ntx, sg.nty, sg.zlen,
-                                                xcd_remap(), fa);
+                                                out, w, c, rk, sg, fa);
             }
         });
     };
@@ -859,8 +857,7 @@ hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fi
                 const int res = resident_blocks<K::template at<2>::fn>(k.tx * k.ty);
                 const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
                 return launch_s<K::template at>(s, dim3(sg.blocks), dim3(k.tx * k.ty), st, g, in,
-                                                out, w, dv, c, rk, sg.ntx, sg.nty, sg.zlen,
-                                                xcd_remap(), fa);
+                                                out, w, dv, c, rk, sg, fa);
             }
         });
     };
