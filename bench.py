@@ -145,8 +145,8 @@ def batch_form(torch, fd6, si, steps, layout="aos"):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     timings = {}
-    for tile in (1, 4, 6, 8):
-        for zc in (0, 32):
+    for tile in (4, 6, 8, 13):
+        for zc in (0, 32, 48, 64):
             b.set_schedule(tile, zc)
             b.step(1)
             e0.record(b.stream)

@@ -268,7 +268,8 @@ int fd6_batch_init_fields(fd6_batch *batch, int32_t box, const double *lnrho, co
 
 /* Kernel shape (1 .. fd6_tile_count()-1, a z-sweep shape) and z-chunk length
  * of the work items (0 = whole box); rebuilds the work list and drops any
- * captured graph.  Default: shape 3 (32 x 8), whole boxes. */
+ * captured graph.  Default: shape 8 (32 x 8, two planes ahead), z chunks of
+ * 64 planes. */
 int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
 
 /* enable != 0 (default): steps replay a captured graph of the 3 substeps;

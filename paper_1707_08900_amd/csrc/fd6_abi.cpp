@@ -85,8 +85,8 @@ struct fd6_box {
 struct fd6_batch {
     int n = 0;
     int precision = 0;
-    int tile = 4;  // 32 x 8 z-sweep
-    int zchunk = 0;  // 0: whole box per work item
+    int tile = 8;     // 32 x 8 z-sweep, two planes ahead
+    int zchunk = 64;  // planes per work item (0: whole box)
     bool aos = false;  // every box in the array-of-structures layout
     bool use_graph = true;
     hipStream_t stream = nullptr;   // caller's stream (graph launches, transfers)

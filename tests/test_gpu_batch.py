@@ -29,7 +29,8 @@ def run_batch(fd6, ws, precision, nsteps, tile=3, zchunk=0, graph=True):
     b.set_params([(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt) for w in ws])
     for i, w in enumerate(ws):
         b.init_fields(i, w.fields)
-    b.set_schedule(tile, zchunk)
+    if tile is not None:
+        b.set_schedule(tile, zchunk)
     b.set_graph(graph)
     b.step(nsteps)
     out = [b.get_fields(i) for i in range(len(ws))]
@@ -51,12 +52,13 @@ def run_single(fd6, w, precision, nsteps, tile):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("tile,zchunk", [(3, 0), (1, 8), (4, 0)])
+@pytest.mark.parametrize("tile,zchunk", [(3, 0), (1, 8), (4, 0), (None, None)])
 def test_batch_equals_single_box_runs_bitwise(fd6, precision, tile, zchunk):
+    """(None, None): the default schedule, shape 8 with 64-plane chunks."""
     ws = small_ensemble()
     out, red = run_batch(fd6, ws, precision, 3, tile, zchunk)
     for i, w in enumerate(ws):
-        ref, rref = run_single(fd6, w, precision, 3, tile)
+        ref, rref = run_single(fd6, w, precision, 3, 8 if tile is None else tile)
         for a, b in zip(out[i], ref):
             assert np.array_equal(a, b), (i, w.shape)
         assert red[i] == rref
