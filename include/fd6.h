@@ -272,6 +272,22 @@ int fd6_batch_init_fields(fd6_batch *batch, int32_t box, const double *lnrho, co
  * 64 planes. */
 int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
 
+/* Autotuner of the ensemble schedule (the shape and chunk choice is the
+ * caller's tuning concern, not the method's): times every z-sweep shape the
+ * ensemble's layout takes with z-chunk lengths 0 (whole boxes), 32, 48 and 64
+ * -- one warm-up step, then 3 timed steps each, HIP events on the ensemble's
+ * stream -- and keeps the fastest.  Advances every box by 4 steps per
+ * candidate: call it before the fields of the actual run are set, or set
+ * them again afterwards.  cache_path (may be NULL) names a text file of
+ * "key tile zchunk" lines, keyed by device name, precision, layout and box
+ * shapes: a cached entry is applied without timing, a new result is appended
+ * (a file that cannot be opened is ignored).  FD6_ESTATE before parameters
+ * and fields are set.  Synchronises. */
+int fd6_batch_tune(fd6_batch *batch, const char *cache_path);
+
+/* The current schedule (set or tuned). */
+int fd6_batch_get_schedule(const fd6_batch *batch, int32_t *tile, int32_t *zchunk);
+
 /* enable != 0 (default): steps replay a captured graph of the 3 substeps;
  * 0: the same kernels are launched directly. */
 int fd6_batch_set_graph(fd6_batch *batch, int32_t enable);

@@ -35,6 +35,7 @@ ABI_SYMBOLS = (
     "fd6_get_timing",
     "fd6_last_error", "fd6_batch_workspace_bytes", "fd6_batch_create", "fd6_batch_destroy",
     "fd6_batch_set_params", "fd6_batch_init_fields", "fd6_batch_set_schedule",
+    "fd6_batch_tune", "fd6_batch_get_schedule",
     "fd6_batch_set_graph", "fd6_batch_step", "fd6_batch_get_fields", "fd6_batch_reduce",
     "fd6_batch_last_error",
 )
@@ -105,6 +106,9 @@ def _declare(lib):
         "fd6_batch_set_params": (I, [P, ctypes.POINTER(Fd6Params)]),
         "fd6_batch_init_fields": (I, [P, ctypes.c_int32, D, D, D, D]),
         "fd6_batch_set_schedule": (I, [P, ctypes.c_int32, ctypes.c_int32]),
+        "fd6_batch_tune": (I, [P, ctypes.c_char_p]),
+        "fd6_batch_get_schedule": (I, [P, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
         "fd6_batch_set_graph": (I, [P, ctypes.c_int32]),
         "fd6_batch_step": (I, [P, ctypes.c_int32]),
         "fd6_batch_get_fields": (I, [P, ctypes.c_int32, D, D, D, D]),
@@ -357,6 +361,20 @@ class Batch:
 
     def set_schedule(self, tile: int, zchunk: int = 0):
         self._check(self.lib.fd6_batch_set_schedule(self.h, tile, zchunk), "fd6_batch_set_schedule")
+
+    def get_schedule(self):
+        t, z = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.fd6_batch_get_schedule(self.h, ctypes.byref(t), ctypes.byref(z)),
+                    "fd6_batch_get_schedule")
+        return t.value, z.value
+
+    def tune(self, cache_path: Optional[str] = None):
+        """Time the schedules in the library's autotuner and keep the fastest
+        (advances every box; set the fields again afterwards).  Returns
+        (tile, zchunk)."""
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.fd6_batch_tune(self.h, path), "fd6_batch_tune")
+        return self.get_schedule()
 
     def set_graph(self, enable: bool):
         self._check(self.lib.fd6_batch_set_graph(self.h, 1 if enable else 0), "fd6_batch_set_graph")

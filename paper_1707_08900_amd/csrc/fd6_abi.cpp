@@ -875,6 +875,69 @@ int batch_reduce(fd6_batch* b, fd6_reductions* out) {
     return bad ? FD6_ENONFINITE : FD6_OK;
 }
 
+
+// ---- ensemble autotuner ----------------------------------------------------
+// Candidate z-chunk lengths (0: whole boxes) and timed steps per candidate.
+constexpr int kBatchTuneChunks[] = {0, 32, 48, 64};
+constexpr int kBatchTuneSteps = 3;
+
+// Two timing events, destroyed with the scope.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t create() {
+        hipError_t e = hipEventCreate(&a);
+        return e != hipSuccess ? e : hipEventCreate(&b);
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Cache key of an ensemble: device name, precision, layout, box count and a
+// 64-bit FNV-1a hash of the box shapes (one token, no spaces).
+std::string batch_tune_key(const fd6_batch* b) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string name = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        name = prop.name;
+    for (char& c : name)
+        if (c == ' ' || c == '\t') c = '_';
+    uint64_t h = 1469598103934665603ull;
+    for (const fd6_desc& d : b->desc)
+        for (int v : {d.nx, d.ny, d.nz}) {
+            for (int k = 0; k < 4; ++k) {
+                h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+                h *= 1099511628211ull;
+            }
+        }
+    char buf[96];
+    snprintf(buf, sizeof buf, "|p%d|%s|n%d|%016llx", b->precision, b->aos ? "aos" : "soa", b->n,
+             (unsigned long long)h);
+    return name + buf;
+}
+
+// Cache file: one "key tile zchunk" line per ensemble; the last match wins.
+bool read_tune_cache(const char* path, const std::string& key, int* tile, int* zchunk) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char k[512];
+    int t = 0, z = 0;
+    bool found = false;
+    while (fscanf(f, "%511s %d %d", k, &t, &z) == 3)
+        if (key == k) *tile = t, *zchunk = z, found = true;
+    fclose(f);
+    return found;
+}
+
+void write_tune_cache(const char* path, const std::string& key, int tile, int zchunk) {
+    FILE* f = fopen(path, "a");
+    if (!f) return;  // the cache is an optimisation only
+    fprintf(f, "%s %d %d\n", key.c_str(), tile, zchunk);
+    fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1294,6 +1357,59 @@ int fd6_batch_step(fd6_batch* b, int32_t nsteps) {
             using T = std::remove_pointer_t<decltype(t)>;
             using TW = std::remove_pointer_t<decltype(tw)>;
             return batch_steps<T, TW>(b, nsteps);
+        });
+    });
+}
+
+int fd6_batch_get_schedule(const fd6_batch* b, int32_t* tile, int32_t* zchunk) {
+    if (!b || !tile || !zchunk) return FD6_EINVAL;
+    *tile = b->tile;
+    *zchunk = b->zchunk;
+    return FD6_OK;
+}
+
+int fd6_batch_tune(fd6_batch* b, const char* cache_path) {
+    if (!b) return FD6_EINVAL;
+    if (!b->have_params) return FD6_ESTATE;
+    for (int i = 0; i < b->n; ++i)
+        if (!b->have_fields[i]) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        const std::string key = batch_tune_key(b);
+        int tile = 0, zchunk = 0;
+        if (cache_path && read_tune_cache(cache_path, key, &tile, &zchunk) &&
+            fd6_batch_set_schedule(b, tile, zchunk) == FD6_OK)
+            return FD6_OK;
+        return batch_dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            EventPair ev;
+            HIPCHK(b, ev.create());
+            float best_ms = -1.0f;
+            int best_tile = b->tile, best_zc = b->zchunk;
+            int rc = FD6_OK;
+            for (int cand = 1; cand < substep55_tile_count() && rc == FD6_OK; ++cand) {
+                int tx, ty;
+                if (substep55_tile_dims(cand, &tx, &ty) != 0) continue;
+                if (b->aos && !substep55_aos_tile_ok(cand)) continue;
+                for (int zc : kBatchTuneChunks) {
+                    b->tile = cand;
+                    b->zchunk = zc;
+                    if ((rc = build_items<T, TW>(b)) != FD6_OK) break;
+                    if ((rc = batch_steps<T, TW>(b, 1)) != FD6_OK) break;  // warm-up, capture
+                    HIPCHK(b, hipEventRecord(ev.a, b->stream));
+                    if ((rc = batch_steps<T, TW>(b, kBatchTuneSteps)) != FD6_OK) break;
+                    HIPCHK(b, hipEventRecord(ev.b, b->stream));
+                    HIPCHK(b, hipEventSynchronize(ev.b));
+                    float ms = 0.0f;
+                    HIPCHK(b, hipEventElapsedTime(&ms, ev.a, ev.b));
+                    if (best_ms < 0.0f || ms < best_ms) best_ms = ms, best_tile = cand, best_zc = zc;
+                }
+            }
+            b->tile = best_tile;
+            b->zchunk = best_zc;
+            if (rc == FD6_OK) rc = build_items<T, TW>(b);
+            if (rc == FD6_OK && cache_path) write_tune_cache(cache_path, key, best_tile, best_zc);
+            return rc;
         });
     });
 }

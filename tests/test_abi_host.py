@@ -185,3 +185,11 @@ def test_batch_validation(pkg):
         assert lib.fd6_batch_get_fields(h, 0, buf, buf, buf, buf) == -2
     finally:
         assert lib.fd6_batch_destroy(h) == 0
+
+
+def test_batch_tuner_argument_checks(pkg):
+    lib = pkg.library()
+    t, z = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.fd6_batch_tune(None, None) == -1
+    assert lib.fd6_batch_tune(None, b"/nonexistent/cache") == -1
+    assert lib.fd6_batch_get_schedule(None, ctypes.byref(t), ctypes.byref(z)) == -1

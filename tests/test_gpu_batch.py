@@ -96,3 +96,31 @@ def test_uneven_ensemble_sample(fd6, orc):
         ref = orc.rk3(inp, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1)
         err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(out[i], ref))
         assert err <= 1e-5, (i, err)
+
+
+def test_tuner_picks_a_valid_schedule_and_caches_it(fd6, tmp_path):
+    """The library's autotuner: the chosen schedule is a z-sweep shape with
+    one of the candidate chunk lengths, the ensemble still equals its
+    single-box runs with that shape, and a second tuner call on the same
+    ensemble takes the cached choice."""
+    ws = small_ensemble()
+    cache = str(tmp_path / "tune.txt")
+    b = fd6.Batch([w.shape for w in ws], "fp32", layout="aos")
+    b.set_params([(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt) for w in ws])
+    for i, w in enumerate(ws):
+        b.init_fields(i, w.fields)
+    tile, zc = b.tune(cache)
+    assert 1 <= tile < fd6.tile_count() and tile != 9 and zc in (0, 32, 48, 64)
+    lines = open(cache).read().split("\n")
+    assert len([ln for ln in lines if ln]) == 1 and lines[0].endswith(f" {tile} {zc}")
+    b.set_schedule(1, 8)
+    assert b.tune(cache) == (tile, zc)  # from the cache
+    assert len([ln for ln in open(cache).read().split("\n") if ln]) == 1
+    for i, w in enumerate(ws):
+        b.init_fields(i, w.fields)
+    b.step(2)
+    for i, w in enumerate(ws):
+        ref, _ = run_single(fd6, w, "fp32", 2, tile)
+        for x, y in zip(b.get_fields(i), ref):
+            assert np.array_equal(x, y), (i, w.shape)
+    b.close()
