@@ -42,7 +42,7 @@ struct fd6_box {
     double* staging = nullptr;
     long long staging_elems = 0;
     int cur = 0;
-    int tile = 2;  // 64 x 8 z-sweep
+    int tile = 6;  // z-sweep shape; fd6_create picks it by precision
     int zchunk = 0;  // z-sweep chunk length, 0: automatic
     bool ghosts_ok[2] = {false, false};  // ghost zone of each state set is current
     std::string err;
@@ -976,6 +976,9 @@ int fd6_create(const fd6_desc* desc, void* d_ws, size_t bytes, void* stream, fd6
     return guarded((fd6_box*)nullptr, [&]() -> int {
         fd6_box* b = new fd6_box();
         b->desc = *desc;
+        // the fastest shapes at 512^3: 64 x 8 for FP32 state, 32 x 8 for FP64
+        // (whose 512-thread shapes spill), both two planes ahead
+        b->tile = desc->precision == FD6_FP64 ? 8 : 6;
         b->geom = p.g;
         b->stream = static_cast<hipStream_t>(stream);
         b->ws = static_cast<char*>(d_ws);
