@@ -4,8 +4,15 @@ for isothermal compressible hydrodynamics (Pekkila et al. 2017).
 This module is a thin ctypes binding over ``libfd6.so`` (C ABI declared in
 ``include/fd6.h``): argument marshalling only.  Every step of the computation
 runs in the library's HIP kernels; PyTorch provides the device workspace and
-the HIP stream.  There is no CPU fallback: without the built library the
-import fails, and without a GPU creating a box fails.
+the HIP stream.  There is no CPU fallback: without the built library every
+entry point raises ImportError (``library()``), and without a GPU creating a
+box fails.
+
+Box: one periodic box (55- or 19-point method, FP64 / FP32 / FP32 + FP64 RK3
+register, state stored per field or as an array of structures).  Batch: an
+ensemble of boxes advanced by one persistent launch per substep, with the
+library's schedule autotuner.  tune.tune(): the kernel-shape autotuner of a
+box.
 """
 from __future__ import annotations
 

@@ -4,7 +4,9 @@
 // two sets of four ghosted state fields (in / out of a substep, swapped by
 // pointer as in Algorithm 2), the four RK3 register fields w, the divergence
 // field of the 19-point method, reduction partials, and an FP64 staging area
-// for host transfers.  No device memory is allocated by the library.
+// for host transfers.  In the array-of-structures layout each state set, and
+// w, is one array of 4-value points instead (same bytes).  No device memory
+// is allocated by the library.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

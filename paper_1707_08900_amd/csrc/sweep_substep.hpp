@@ -23,8 +23,13 @@
 //  * Output plane z is finished 3 planes behind the load front: the right-hand
 //    side is assembled in registers and the RK3 update is written out.
 //  * The z loop is unrolled by 8 so every ring index is a compile-time
-//    register; the workgroup-to-tile map keeps neighbouring tiles on one XCD
-//    so y-halo rows are served from that XCD's L2.
+//    register; the workgroup-to-tile map gives each XCD a near-square block
+//    of neighbouring tiles, so most halo cells are served from its L2.
+//  * Template switches: VS = 4 reads and writes the array-of-structures
+//    layout (one 16-byte access per cell and field set); NT streams the new
+//    state and the RK3 register past the caches; FRC adds the external
+//    force; RED accumulates the FP64 diagnostics; P19 turns the sweep into
+//    pass 1 of the 19-point method.
 #pragma once
 
 #include "sweep_common.hpp"
