@@ -116,22 +116,31 @@ def test_aos_rhs_and_diagnostics_match(fd6, precision):
 
 
 def test_aos_forced_and_graph_steps_match(fd6):
+    """Forced steps, eager and replayed, the last one with the fused
+    diagnostics (the forced, reducing, AoS instantiation of the sweep)."""
+    import torch
     w = si.noise_box((24, 30, 36), seed=8)
     draws = si.forcing_draws(4, 1.0, 2.0, 0.05, seed=2)
-    res = {}
+    res, reds = {}, {}
     for lay in ("soa", "aos"):
         for graph in (False, True):
             b = make(fd6, w, "fp32", lay, tile=12)
             b.set_graph(graph)
-            for d in draws:
+            red = torch.zeros(8, dtype=torch.float64, device=b.device)
+            for i, d in enumerate(draws):
                 b.set_forcing(d)
-                b.step(1)
+                if i + 1 < len(draws):
+                    b.step(1)
+                else:
+                    b.step_reduce(1, red)
             res[(lay, graph)] = b.get_fields()
+            reds[(lay, graph)] = red.cpu().numpy()[:5]
             b.close()
     want = res[("soa", False)]
     for key, got in res.items():
         for q in range(4):
             assert np.array_equal(got[q], want[q]), key
+        assert np.array_equal(reds[key], reds[("soa", False)]), key
 
 
 def test_aos_sound_wave_stays_on_the_closed_form(fd6):
