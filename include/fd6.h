@@ -178,10 +178,11 @@ int fd6_rhs(fd6_box *box, double *r_lnrho, double *r_ux, double *r_uy, double *r
  * different xy tile shapes, load pipelines and cache policies (most shapes
  * stream the new state and the RK register past the caches; the last ones
  * keep them cached, which pays when the whole state fits in the device's
- * last-level cache).  Results agree up to rounding
- * order (the z-sweep shapes bit for bit with each other); the choice only
- * changes speed (see the autotuner).  Default: 6 (64 x 8, two planes ahead)
- * for FP32 state, 8 (32 x 8, two planes ahead) for FP64. */
+ * last-level cache).  Results agree up to rounding order (the z-sweep shapes
+ * bit for bit with each other); the choice only changes speed (see the
+ * autotuner).  FD6_EINVAL for an index out of range; FD6_EUNSUPPORTED for a
+ * shape the box's layout does not take (FD6_LAYOUT_AOS).  Default: 6 (64 x 8,
+ * two planes ahead) for FP32 state, 8 (32 x 8, two planes ahead) for FP64. */
 int fd6_tile_count(void);
 int fd6_set_tile(fd6_box *box, int32_t tile);
 
