@@ -367,9 +367,10 @@ int do_substep(fd6_box* b, int s, const RKCoef<TW>& rk, double* red_out = nullpt
             });
             if (rc) return rc;
         }
+        double* parts = (red_out && s == 3) ? b->partials : nullptr;
         rc = timed(b, b->ev_kernel, [&]() -> int {
-            HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, s, b->tile, b->zchunk,
-                                                b->stream)));
+            HIPCHK(b, (launch_pass19b<T, TW>(g, dv, out, w, c, rk, s, b->tile, b->zchunk, parts,
+                                             kFusedPartials, &nparts, b->stream)));
             return FD6_OK;
         });
         if (rc) return rc;

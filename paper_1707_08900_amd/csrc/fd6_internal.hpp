@@ -188,10 +188,12 @@ template <typename T, typename TW>
 hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
                                 T* div, const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile,
                                 int zchunk, const ForceArgs<T>* frc, hipStream_t st);
+// With partials != nullptr, substep 3 of a z-sweep shape also writes the FP64
+// diagnostics partials of the new state (as launch_substep55 does).
 template <typename T, typename TW>
 hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
                           const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                          hipStream_t st);
+                          double* partials, int part_cap, int* nparts, hipStream_t st);
 
 // FP64 reductions: per-block partials then one fixed-order final block.
 constexpr int kReduceBlocks = 1024;

@@ -127,6 +127,7 @@ struct Pass2Regs {
     T dx[4], dy[4];  // x / y first derivatives of d, ring of 4 planes
     T pf;        // prefetched interior value of the next plane
     T ph[NH];    // prefetched halo values of the next plane
+    double red[5];  // RED: FP64 diagnostics of the thread's column
 };
 
 // As in the 55-point sweep, no memory operation of a step sits behind a
@@ -141,7 +142,7 @@ __device__ __forceinline__ void pass2_prefetch(Pass2Regs<T, NH>& R,
     for (int h = 0; h < NH; ++h) R.ph[h] = bload((T*)nullptr, rs, X.goff_h[h]);
 }
 
-template <int PH, int S, bool NT, typename T, typename TW, int TX, int TY, int NH>
+template <int PH, int S, bool NT, bool RED, typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Regs<T, NH>& R,
                                            const SweepCtx<T, TX, TY>& X, T* lds, const Geom& g,
                                            const T* dv, const Fields4<T>& out,
@@ -160,6 +161,9 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
     constexpr int CP = NT ? kNonTemporal : 0;
     T ov[3] = {T(0), T(0), T(0)};
     TW wv[3] = {TW(0), TW(0), TW(0)};
+    // RED (substep 3): lnrho of the output point, final since pass 1
+    T lr = T(0);
+    if constexpr (RED) lr = bload((T*)nullptr, plane_rsrc(out.f[0] + ocorner, ob), X.lane_o);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         ov[i] = bload<CP>((T*)nullptr, plane_rsrc(out.f[1 + i] + ocorner, ob), X.lane_o);
@@ -188,28 +192,40 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
                      cf.d1[2][2] * (R.q[sl8(PH)] - R.q[sl8(PH - 6)]);
         constexpr int DO = (PH + 1) & 3;  // slot of plane p - 3
         const T gd[3] = {R.dx[DO], R.dy[DO], dz};
+        T un[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const TW tq = cgd * TW(gd[i]);
             if constexpr (S != 3)
                 bstore<CP>(wv[i] + tq, plane_rsrc(w.f[1 + i] + (long long)o * g.wplane, wb),
                            X.lane_w);
-            bstore<CP>(T(TW(ov[i]) + rk.beta * tq), plane_rsrc(out.f[1 + i] + ocorner, ob),
-                       X.lane_o);
+            un[i] = T(TW(ov[i]) + rk.beta * tq);
+            bstore<CP>(un[i], plane_rsrc(out.f[1 + i] + ocorner, ob), X.lane_o);
         }
+        if constexpr (RED)
+            red_point(R.red, outstep && X.lane_o != kDropOffset, lr, un[0], un[1], un[2]);
     }
 }
 
-template <typename T, typename TW, int TX, int TY, int S, bool NT>
+// RED (substep 3 only): also the FP64 diagnostics of the new state, one
+// partial per workgroup at part[blockIdx.x * kReduceSlots ...].
+template <typename T, typename TW, int TX, int TY, int S, bool NT, bool RED = false>
 __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __restrict__ dv,
                                                           Fields4<T> out, Fields4<TW> w,
                                                           Coef<T> cf, RKCoef<TW> rk, TW cgd,
-                                                          SweepGrid m) {
+                                                          SweepGrid m, double* part) {
+    static_assert(!RED || S == 3, "diagnostics of the final substep only");
     using Sh = SweepShape<T, TX, TY>;
     constexpr int NH = Sh::NH;
     __shared__ T lds[2 * Sh::FS];
     const TileXY tl = sweep_tile_of(g, TX, TY, m);
-    if (tl.zb >= tl.ze) return;
+    if (tl.zb >= tl.ze) {  // not produced by sweep_grid; keeps every partial defined
+        if constexpr (RED) {
+            if (threadIdx.x == 0)
+                for (int i = 0; i < 5; ++i) part[(size_t)blockIdx.x * kReduceSlots + i] = 0.0;
+        }
+        return;
+    }
     SweepCtx<T, TX, TY> X;
     sweep_ctx_init<T, TW, TX, TY, false>(X, g, tl.tx, tl.ty);
     Pass2Regs<T, NH> R;
@@ -217,19 +233,22 @@ __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __res
     for (int s = 0; s < 8; ++s) R.q[s] = T(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) R.dx[s] = R.dy[s] = T(0);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) R.red[i] = 0.0;
     const int zb = tl.zb;
     const int nplanes = (tl.ze - zb) + 2 * kR;
     pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, zb - kR), X.plane_bytes);
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        pass2_step<0, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<1, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<2, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<3, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<4, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<5, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<6, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
-        pass2_step<7, S, NT>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<0, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<1, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<2, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<3, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<4, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<5, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<6, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
+        pass2_step<7, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
     }
+    if constexpr (RED) red_store_n<Sh::NW>(R.red, part);
 }
 
 }  // namespace
@@ -263,7 +282,8 @@ hipError_t launch_pass19a(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<
 template <typename T, typename TW>
 hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<TW> w,
                           const Coef<T>& c, const RKCoef<TW>& rk, int s, int tile, int zchunk,
-                          hipStream_t st) {
+                          double* partials, int part_cap, int* nparts, hipStream_t st) {
+    if (nparts) *nparts = 0;
     const TW cgd = TW((double)rk.dt * c.nu3);
     return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
         constexpr TileCfg k = kTiles[decltype(I)::value];
@@ -277,18 +297,39 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
                 resident_blocks<substep19_pass2<T, TW, k.tx, k.ty, 2, k.nt>>(k.tx * k.ty);
             const SweepGrid sg = sweep_grid(g, k.tx, k.ty, zchunk, res);
             const dim3 grid(sg.blocks), block(k.tx * k.ty);
+            // Fuse the diagnostics unless that leaves fewer than 2 waves per
+            // SIMD: this light one-field sweep loses little occupancy that
+            // matters, while the standalone pass re-reads the whole state
+            // (measured at 512^3: 4.7% of the FP32 19-point step).
+            static const bool fuse_ok = [] {
+                int a = 0, b = 0;
+                const int blk = k.tx * k.ty;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &a, substep19_pass2<T, TW, k.tx, k.ty, 3, k.nt, true>, blk, 0) !=
+                        hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &b, substep19_pass2<T, TW, k.tx, k.ty, 3, k.nt>, blk, 0) != hipSuccess)
+                    return false;
+                return a > 0 && (a >= b || a * (blk / 64) >= 8);
+            }();
             switch (s) {
             case 1:
                 hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 1, k.nt>), grid, block, 0,
-                                   st, g, div, out, w, c, rk, cgd, sg);
+                                   st, g, div, out, w, c, rk, cgd, sg, nullptr);
                 break;
             case 2:
                 hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 2, k.nt>), grid, block, 0,
-                                   st, g, div, out, w, c, rk, cgd, sg);
+                                   st, g, div, out, w, c, rk, cgd, sg, nullptr);
                 break;
             default:
-                hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 3, k.nt>), grid, block, 0,
-                                   st, g, div, out, w, c, rk, cgd, sg);
+                if (partials && nparts && fuse_ok && sg.blocks <= part_cap) {
+                    hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 3, k.nt, true>), grid,
+                                       block, 0, st, g, div, out, w, c, rk, cgd, sg, partials);
+                    *nparts = sg.blocks;
+                } else {
+                    hipLaunchKernelGGL((substep19_pass2<T, TW, k.tx, k.ty, 3, k.nt>), grid, block,
+                                       0, st, g, div, out, w, c, rk, cgd, sg, nullptr);
+                }
                 break;
             }
         }
@@ -302,7 +343,7 @@ hipError_t launch_pass19b(const Geom& g, const T* div, Fields4<T> out, Fields4<T
                                               int, const ForceArgs<T>*, hipStream_t);          \
     template hipError_t launch_pass19b<T, TW>(const Geom&, const T*, Fields4<T>, Fields4<TW>,   \
                                               const Coef<T>&, const RKCoef<TW>&, int, int,     \
-                                              int, hipStream_t);
+                                              int, double*, int, int*, hipStream_t);
 FD6_INST19(double, double)
 FD6_INST19(float, float)
 FD6_INST19(float, double)

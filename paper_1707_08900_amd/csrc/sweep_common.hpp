@@ -304,6 +304,57 @@ __device__ __forceinline__ TileXY sweep_tile_of(const Geom& g, int TX, int TY,
     return TileXY{tix * TX, tiy * TY, zb, min(zb + m.zlen, g.nz)};
 }
 
+// FP64 diagnostics of the new state (the quantities of the standalone
+// reduction): per thread, red = {sum rho, sum rho |u|^2 / 2, sum lnrho,
+// max |u|^2, non-finite count}; invalid points (no output, outside the box)
+// add nothing.
+__device__ __forceinline__ void red_point(double red[5], bool valid, double lr, double ux,
+                                          double uy, double uz) {
+    const double rho = exp(lr);
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    const bool finite = isfinite(lr) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+    red[0] += valid ? rho : 0.0;
+    red[1] += valid ? 0.5 * rho * u2 : 0.0;
+    red[2] += valid ? lr : 0.0;
+    red[3] = (valid && u2 > red[3]) ? u2 : red[3];
+    red[4] += (valid && !finite) ? 1.0 : 0.0;
+}
+
+// Combines the per-thread diagnostics of a workgroup in a fixed order (xor
+// tree within each wave, then waves in order) and stores the partial:
+// sums for slots 0-2 and 4, the maximum for slot 3.
+template <int NW>
+__device__ __forceinline__ void red_store_n(double v[5], double* part) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            const double o = __shfl_xor(v[i], off, 64);
+            v[i] = i == 3 ? (o > v[i] ? o : v[i]) : v[i] + o;
+        }
+    }
+    __shared__ double sw[NW][5];
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) sw[wv][i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < NW; ++k)
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                a[i] = i == 3 ? (sw[k][i] > a[i] ? sw[k][i] : a[i]) : a[i] + sw[k][i];
+        double* p = part + (size_t)blockIdx.x * kReduceSlots;
+        p[0] = a[0];
+        p[1] = a[1];
+        p[2] = a[2];
+        p[3] = sqrt(a[3]);  // max |u| = sqrt(max |u|^2): sqrt is monotonic
+        p[4] = a[4];
+    }
+}
+
 // Kernel shapes of the z-sweep substeps.  Index 0 is the direct kernel (one
 // thread per point, taps from the ghost zone); the others are (TX, TY) column
 // tiles.  pd: how many planes ahead the register loader fetches (1, 2 or 4;

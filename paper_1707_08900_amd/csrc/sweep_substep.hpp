@@ -410,18 +410,9 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             bstore(J[0][0] + J[1][1] + J[2][2], plane_rsrc(dv + ocorner, ob), X.lane_o);
         // FP64 diagnostics of the new state, from the values just stored (the
         // same per-point quantities as the standalone reduction)
-        if constexpr (RED) {
-            const bool valid = outstep && X.lane_o != kDropOffset;
-            const double lr = vout[0], ux = vout[1], uy = vout[2], uz = vout[3];
-            const double rho = exp(lr);
-            const double u2 = ux * ux + uy * uy + uz * uz;
-            const bool finite = isfinite(lr) && isfinite(ux) && isfinite(uy) && isfinite(uz);
-            R.red[0] += valid ? rho : 0.0;
-            R.red[1] += valid ? 0.5 * rho * u2 : 0.0;
-            R.red[2] += valid ? lr : 0.0;
-            R.red[3] = (valid && u2 > R.red[3]) ? u2 : R.red[3];
-            R.red[4] += (valid && !finite) ? 1.0 : 0.0;
-        }
+        if constexpr (RED)
+            red_point(R.red, outstep && X.lane_o != kDropOffset, vout[0], vout[1], vout[2],
+                      vout[3]);
     }
 
     // (C) the rest of plane p for this column: x / y first derivatives of the
@@ -546,41 +537,6 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
 // One tile-chunk: columns [x0, x0 + TX) x [y0, y0 + TY) of the box, output
 // planes [zb, ze).  Every thread of the workgroup calls it with the same
 // arguments.  P19: pass 1 of the 19-point method (dv receives the divergence).
-// Combines the per-thread diagnostics of a workgroup in a fixed order (xor
-// tree within each wave, then waves in order) and stores the partial:
-// sums for slots 0-2 and 4, the maximum for slot 3.
-template <int NW>
-__device__ __forceinline__ void red_store_n(double v[5], double* part) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) {
-            const double o = __shfl_xor(v[i], off, 64);
-            v[i] = i == 3 ? (o > v[i] ? o : v[i]) : v[i] + o;
-        }
-    }
-    __shared__ double sw[NW][5];
-    const int wv = threadIdx.x / 64;
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int i = 0; i < 5; ++i) sw[wv][i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < NW; ++k)
-#pragma unroll
-            for (int i = 0; i < 5; ++i)
-                a[i] = i == 3 ? (sw[k][i] > a[i] ? sw[k][i] : a[i]) : a[i] + sw[k][i];
-        double* p = part + (size_t)blockIdx.x * kReduceSlots;
-        p[0] = a[0];
-        p[1] = a[1];
-        p[2] = a[2];
-        p[3] = sqrt(a[3]);  // max |u| = sqrt(max |u|^2): sqrt is monotonic
-        p[4] = a[4];
-    }
-}
-
 // RED: also reduce the FP64 diagnostics of the output and store this
 // workgroup's partial at part[blockIdx.x * kReduceSlots ...].
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS,

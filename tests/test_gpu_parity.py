@@ -299,15 +299,17 @@ def test_device_init_and_export(fd6):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 6, 9])
-def test_step_reduce_matches_standalone_and_oracle(fd6, orc, tile):
-    """Diagnostics of the last step (fused into substep 3 for the z-sweep
-    shapes, a separate pass for the direct shape) equal fd6_reduce of the
-    same state up to summation order, and the oracle's reduction of the
-    oracle's state; max |u| and the non-finite count exactly."""
+@pytest.mark.parametrize("variant,tile", [("55p", 0), ("55p", 1), ("55p", 2), ("55p", 6),
+                                          ("55p", 9), ("19p", 0), ("19p", 6), ("19p", 8)])
+def test_step_reduce_matches_standalone_and_oracle(fd6, orc, variant, tile):
+    """Diagnostics of the last step (fused into substep 3 -- the 55-point
+    sweep, or pass 2 of the 19-point method -- for the z-sweep shapes, a
+    separate pass for the direct shape) equal fd6_reduce of the same state up
+    to summation order, and the oracle's reduction of the oracle's state;
+    max |u| and the non-finite count exactly."""
     import torch
     w = si.noise_box((24, 20, 36), seed=13)
-    box = fd6.Box(w.shape, "fp64")
+    box = fd6.Box(w.shape, "fp64", variant)
     box.set_tile(tile)
     box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
     box.init_fields(w.fields)
@@ -315,7 +317,7 @@ def test_step_reduce_matches_standalone_and_oracle(fd6, orc, tile):
     box.step_reduce(2, red)
     fused = red.cpu().numpy()
     alone = box.reduce()
-    ref_state = orc.rk3(w.fields, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 2)
+    ref_state = orc.rk3(w.fields, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, variant, 2)
     ref = orc.reduce(ref_state, w.dx, w.dy, w.dz)
     for key, i in (("mass", 0), ("kinetic_energy", 1)):
         assert fused[i] == pytest.approx(alone[key], rel=1e-13)
