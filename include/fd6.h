@@ -192,6 +192,21 @@ int fd6_set_tile(fd6_box *box, int32_t tile);
  * do not depend on it (bit for bit).  FD6_EINVAL if zchunk < 0. */
 int fd6_set_zchunk(fd6_box *box, int32_t zchunk);
 
+/* The current kernel shape and z-chunk length (set or tuned). */
+int fd6_get_schedule(const fd6_box *box, int32_t *tile, int32_t *zchunk);
+
+/* Autotuner of the kernel shape and z-chunk length (a speed choice only):
+ * times every z-sweep shape the box's layout takes with the automatic
+ * z-chunk, then z-chunk lengths 64, 128, 256 (those below nz) and nz for the
+ * fastest shape -- one warm-up and 2 timed steps each, every step with its
+ * FP64 diagnostics as fd6_rk3_step_reduce computes them, HIP events on the
+ * box's stream -- and keeps the fastest pair.  Advances the state by 3 steps
+ * per candidate: call it before the fields of the actual run are set, or set
+ * them again afterwards.  cache_path as for fd6_batch_tune (key: device name,
+ * grid, precision, method, layout).  FD6_ESTATE before parameters and fields
+ * are set.  Synchronises. */
+int fd6_tune(fd6_box *box, const char *cache_path);
+
 /* External force of the momentum equation: one Fourier mode of eq.
  * (forcing), Sec. 6,
  *   f(x) = Re{ N f_k exp(i k.x + i phase) },  N = f0 cs sqrt(|k| cs / dt),

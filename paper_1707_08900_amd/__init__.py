@@ -38,6 +38,7 @@ ABI_SYMBOLS = (
     "fd6_set_stream", "fd6_set_params", "fd6_init_fields", "fd6_init_fields_device",
     "fd6_rk3_step", "fd6_rk3_step_reduce", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
     "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_zchunk", "fd6_set_graph",
+    "fd6_get_schedule", "fd6_tune",
     "fd6_set_forcing", "fd6_set_timing",
     "fd6_get_timing",
     "fd6_last_error", "fd6_batch_workspace_bytes", "fd6_batch_create", "fd6_batch_destroy",
@@ -113,6 +114,9 @@ def _declare(lib):
         "fd6_batch_set_params": (I, [P, ctypes.POINTER(Fd6Params)]),
         "fd6_batch_init_fields": (I, [P, ctypes.c_int32, D, D, D, D]),
         "fd6_batch_set_schedule": (I, [P, ctypes.c_int32, ctypes.c_int32]),
+        "fd6_tune": (I, [P, ctypes.c_char_p]),
+        "fd6_get_schedule": (I, [P, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32)]),
         "fd6_batch_tune": (I, [P, ctypes.c_char_p]),
         "fd6_batch_get_schedule": (I, [P, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
@@ -289,6 +293,21 @@ class Box:
     def set_zchunk(self, zchunk: int):
         """z-chunk length of the sweep kernels (0: automatic)."""
         self._check(self.lib.fd6_set_zchunk(self.h, int(zchunk)), "fd6_set_zchunk")
+
+    def get_schedule(self):
+        """(kernel shape, z-chunk length) currently in use."""
+        t, z = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.fd6_get_schedule(self.h, ctypes.byref(t), ctypes.byref(z)),
+                    "fd6_get_schedule")
+        return t.value, z.value
+
+    def tune(self, cache_path: Optional[str] = None):
+        """The library's autotuner (fd6_tune; advances the state, so set the
+        fields again afterwards).  Returns (tile, zchunk).  tune.tune() is the
+        Python tuner with per-candidate timings."""
+        path = cache_path.encode() if cache_path else None
+        self._check(self.lib.fd6_tune(self.h, path), "fd6_tune")
+        return self.get_schedule()
 
     def set_forcing(self, forcing=None):
         """External force (one mode of eq. forcing) for the following steps:

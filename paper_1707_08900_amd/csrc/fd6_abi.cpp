@@ -921,7 +921,24 @@ std::string batch_tune_key(const fd6_batch* b) {
     return name + buf;
 }
 
-// Cache file: one "key tile zchunk" line per ensemble; the last match wins.
+// Cache key of a single box: device name, grid, precision, method, layout.
+std::string box_tune_key(const fd6_box* b) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string name = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        name = prop.name;
+    for (char& c : name)
+        if (c == ' ' || c == '\t') c = '_';
+    char buf[128];
+    snprintf(buf, sizeof buf, "|%dx%dx%d|p%d|v%d|%s", b->desc.nx, b->desc.ny, b->desc.nz,
+             b->desc.precision, b->desc.variant, b->geom.vs == 4 ? "aos" : "soa");
+    return name + buf;
+}
+
+constexpr int kBoxTuneSteps = 2;
+
+// Cache file: one "key tile zchunk" line per box or ensemble; the last match wins.
 bool read_tune_cache(const char* path, const std::string& key, int* tile, int* zchunk) {
     FILE* f = fopen(path, "r");
     if (!f) return false;
@@ -1231,6 +1248,70 @@ int fd6_set_zchunk(fd6_box* b, int32_t zchunk) {
     if (zchunk != b->zchunk) b->drop_graphs();
     b->zchunk = zchunk;
     return FD6_OK;
+}
+
+int fd6_get_schedule(const fd6_box* b, int32_t* tile, int32_t* zchunk) {
+    if (!b || !tile || !zchunk) return FD6_EINVAL;
+    *tile = b->tile;
+    *zchunk = b->zchunk;
+    return FD6_OK;
+}
+
+int fd6_tune(fd6_box* b, const char* cache_path) {
+    if (!b) return FD6_EINVAL;
+    if (!ready(b)) return FD6_ESTATE;
+    return guarded(b, [&]() -> int {
+        const std::string key = box_tune_key(b);
+        int tile = 0, zchunk = 0;
+        if (cache_path && read_tune_cache(cache_path, key, &tile, &zchunk) &&
+            fd6_set_tile(b, tile) == FD6_OK && fd6_set_zchunk(b, zchunk) == FD6_OK)
+            return FD6_OK;
+        return dispatch(b, [&](auto* t, auto* tw) -> int {
+            using T = std::remove_pointer_t<decltype(t)>;
+            using TW = std::remove_pointer_t<decltype(tw)>;
+            EventPair ev;
+            HIPCHK(b, ev.create());
+            const bool timing = b->timing;
+            b->timing = false;
+            // ms per reducing step of one schedule (one warm-up step first)
+            auto trial = [&](int cand, int zc, float* ms) -> int {
+                if (cand != b->tile || zc != b->zchunk) b->drop_graphs();
+                b->tile = cand;
+                b->zchunk = zc;
+                int rc = do_steps<T, TW>(b, 1, b->result);
+                if (rc) return rc;
+                HIPCHK(b, hipEventRecord(ev.a, b->stream));
+                if ((rc = do_steps<T, TW>(b, kBoxTuneSteps, b->result)) != FD6_OK) return rc;
+                HIPCHK(b, hipEventRecord(ev.b, b->stream));
+                HIPCHK(b, hipEventSynchronize(ev.b));
+                HIPCHK(b, hipEventElapsedTime(ms, ev.a, ev.b));
+                return FD6_OK;
+            };
+            int rc = FD6_OK, best_tile = b->tile, best_zc = b->zchunk;
+            float best_ms = -1.0f, ms = 0.0f;
+            for (int cand = 1; cand < substep55_tile_count() && rc == FD6_OK; ++cand) {
+                if (b->geom.vs == 4 && !substep55_aos_tile_ok(cand)) continue;
+                if ((rc = trial(cand, 0, &ms)) == FD6_OK && (best_ms < 0.0f || ms < best_ms))
+                    best_ms = ms, best_tile = cand, best_zc = 0;
+            }
+            // then explicit chunk lengths for that shape, whole columns included
+            std::vector<int> chunks;
+            for (int zc : {64, 128, 256})
+                if (zc < b->desc.nz) chunks.push_back(zc);
+            chunks.push_back(b->desc.nz);
+            for (int zc : chunks) {
+                if (rc != FD6_OK) break;
+                if ((rc = trial(best_tile, zc, &ms)) == FD6_OK && ms < best_ms)
+                    best_ms = ms, best_zc = zc;
+            }
+            b->timing = timing;
+            if (best_tile != b->tile || best_zc != b->zchunk) b->drop_graphs();
+            b->tile = best_tile;
+            b->zchunk = best_zc;
+            if (rc == FD6_OK && cache_path) write_tune_cache(cache_path, key, best_tile, best_zc);
+            return rc;
+        });
+    });
 }
 
 int fd6_batch_workspace_bytes(int32_t n, const fd6_desc* descs, size_t* bytes) {

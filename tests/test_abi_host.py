@@ -193,3 +193,10 @@ def test_batch_tuner_argument_checks(pkg):
     assert lib.fd6_batch_tune(None, None) == -1
     assert lib.fd6_batch_tune(None, b"/nonexistent/cache") == -1
     assert lib.fd6_batch_get_schedule(None, ctypes.byref(t), ctypes.byref(z)) == -1
+
+
+def test_box_tuner_argument_checks(pkg):
+    lib = pkg.library()
+    t, z = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.fd6_tune(None, None) == -1
+    assert lib.fd6_get_schedule(None, ctypes.byref(t), ctypes.byref(z)) == -1

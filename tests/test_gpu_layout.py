@@ -204,3 +204,30 @@ def test_aos_ensemble_matches_single_boxes(fd6, precision):
                 assert np.array_equal(got[q], want[q]), (tile, i, q)
             assert red[i] == want_red, (tile, i)
     b.close()
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_library_tuner_single_box(fd6, layout, tmp_path):
+    """fd6_tune: a valid schedule for the layout, taken from the cache the
+    second time, and a tuned box reproduces the default shape bit for bit."""
+    w = si.noise_box((40, 24, 36), seed=17)
+    cache = str(tmp_path / "tune.txt")
+    box = make(fd6, w, "fp32", layout)
+    default = box.get_schedule()
+    assert default == (6, 0)
+    tile, zc = box.tune(cache)
+    assert 1 <= tile < fd6.tile_count() and (layout == "soa" or tile != 9)
+    assert zc in (0, 40) or zc in (64, 128, 256)
+    box.set_tile(default[0])
+    box.set_zchunk(default[1])
+    assert box.tune(cache) == (tile, zc)  # from the cache
+    assert len([ln for ln in open(cache).read().split("\n") if ln]) == 1
+    box.init_fields(w.fields)
+    box.step(2)
+    got = box.get_fields()
+    box.close()
+    ref = make(fd6, w, "fp32", layout)
+    ref.step(2)
+    for a, b in zip(got, ref.get_fields()):
+        assert np.array_equal(a, b)
+    ref.close()
