@@ -720,7 +720,11 @@ int build_items(fd6_batch* b) {
     std::vector<long long> cost;
     for (int i = 0; i < b->n; ++i) {
         const Geom& g = b->geom[i];
-        const int zl = b->zchunk > 0 ? std::min(b->zchunk, g.nz) : g.nz;
+        // chunks of at most zchunk planes, split evenly (96 planes with 64-plane
+        // chunks give 48 + 48, not 64 + 32)
+        const int cap = b->zchunk > 0 ? std::min(b->zchunk, g.nz) : g.nz;
+        const int nch = (g.nz + cap - 1) / cap;
+        const int zl = (g.nz + nch - 1) / nch;
         for (int zb = 0; zb < g.nz; zb += zl)
             for (int y0 = 0; y0 < g.ny; y0 += ty)
                 for (int x0 = 0; x0 < g.nx; x0 += tx) {
