@@ -284,9 +284,10 @@ int fd6_batch_init_fields(fd6_batch *batch, int32_t box, const double *lnrho, co
                           const double *uy, const double *uz);
 
 /* Kernel shape (1 .. fd6_tile_count()-1, a z-sweep shape) and z-chunk length
- * of the work items (0 = whole box); rebuilds the work list and drops any
- * captured graph.  Default: shape 8 (32 x 8, two planes ahead), z chunks of
- * 64 planes. */
+ * of the work items: each box's z range is split evenly into chunks of at
+ * most zchunk planes (0 = whole boxes).  Rebuilds the work list and drops any
+ * captured graph.  Default: shape 8 (32 x 8, two planes ahead), chunks of at
+ * most 64 planes. */
 int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
 
 /* Autotuner of the ensemble schedule (the shape and chunk choice is the
