@@ -32,13 +32,28 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic HBM bytes per grid-point update (one full RK3 step), the
 # method's own minimum: state read once per substep, w read when alpha != 0
 # and written when it is needed again, output written once; ghosts and halo
-# re-reads excluded.  55-point: 40 field accesses per step; 19-point: 76.
+# re-reads excluded.  55-point: 40 field accesses per step (16 of them to w);
+# 19-point: 76 (28 to w).
 ALG_BYTES = {("55p", "fp32"): 160, ("55p", "fp64"): 320, ("55p", "fp32_acc64"): 224,
-             ("19p", "fp32"): 304, ("19p", "fp64"): 608}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_substep55_fp32_512.json")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1707_08900_amd", "csrc", f)
-               for f in ("sweep_common.hpp", "sweep_substep.hpp", "substep55_f32.hip",
-                         "substep55_aos_f32.hip")]
+             ("19p", "fp32"): 304, ("19p", "fp64"): 608, ("19p", "fp32_acc64"): 416}
+PREC_TAG = {"fp32": "f32", "fp64": "f64", "fp32_acc64": "f32w64"}
+DTYPE = {"fp32": "f32", "fp64": "f64", "fp32_acc64": "f32 state, f64 RK3 register"}
+PNAME = {"fp32": "FP32", "fp64": "FP64", "fp32_acc64": "FP32 state with FP64 RK3 register"}
+VNAME = {"55p": "55-point fused substep", "19p": "19-point two-pass substep"}
+
+
+def traffic_file(variant, precision, n):
+    """Committed counter record of the headline kernel of one form."""
+    kern = "substep55" if variant == "55p" else "substep19"
+    return os.path.join(ROOT, "profiles", f"traffic_{kern}_{precision}_{n}.json")
+
+
+def kernel_srcs(variant, precision):
+    """Sources whose hash a counter record must match."""
+    t = PREC_TAG[precision]
+    files = ["sweep_common.hpp", "sweep_substep.hpp", f"substep55_{t}.hip"]
+    files += [f"substep55_aos_{t}.hip"] if variant == "55p" else ["substep19.hip"]
+    return [os.path.join(ROOT, "paper_1707_08900_amd", "csrc", f) for f in files]
 
 
 def log(msg):
@@ -53,16 +68,16 @@ def source_sha(paths):
     return h.hexdigest()[:16]
 
 
-def load_traffic(shape, layout):
+def load_traffic(shape, layout, variant="55p", precision="fp32", n=512):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source with the same layout, kernel shape and
     z-chunk length."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(variant, precision, n)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha") != source_sha(KERNEL_SRCS):
+    if t.get("kernel_source_sha") != source_sha(kernel_srcs(variant, precision)):
         return None
     if (t.get("tile"), t.get("zchunk")) != (shape.get("tile"), shape.get("zchunk")):
         return None
@@ -250,8 +265,16 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0,
                     help="z-chunk length with --tile (0: automatic)")
     ap.add_argument("--layout", choices=("aos", "soa"), default="aos",
-                    help="device layout of the headline box's state")
+                    help="device layout of the headline box's state (55-point only)")
+    ap.add_argument("--precision", choices=("fp32", "fp64", "fp32_acc64"), default="fp32",
+                    help="precision form of the headline box (profiling the other forms)")
+    ap.add_argument("--variant", choices=("55p", "19p"), default="55p",
+                    help="method of the headline box (profiling the other forms)")
     a = ap.parse_args()
+    if a.variant == "19p":
+        a.layout = "soa"  # the 19-point passes keep one array per field
+    prec, var = a.precision, a.variant
+    launches_per_step = 3 if var == "55p" else 6
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -287,7 +310,7 @@ def main():
 
     dev_fields = [torch.from_numpy(f).cuda() for f in w.fields]
     red = torch.zeros(8, dtype=torch.float64, device="cuda")
-    box, tuned = make_box(fd6, w, dev_fields, "fp32", "55p", tune=a.tile is None,
+    box, tuned = make_box(fd6, w, dev_fields, prec, var, tune=a.tile is None,
                           layout=a.layout)
     if a.tile is not None:
         box.set_tile(a.tile)
@@ -304,18 +327,20 @@ def main():
     box.close()
     ms_per_step = ev_ms / a.steps
     value = n ** 3 * a.steps / (ev_ms * 1e-3)
-    log(f"fp32 55p {a.layout} {n}^3: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} G updates/s "
+    log(f"{prec} {var} {a.layout} {n}^3: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} G updates/s "
         f"(host wall {wall * 1e3 / a.steps:.3f} ms/step); mass {r[0]:.10e} ke {r[1]:.6e}")
 
-    # dominant kernel: the fused 55-point substep kernel
-    alg_per_launch = n ** 3 * ALG_BYTES[("55p", "fp32")] / 3.0
+    # dominant kernel: the fused 55-point substep kernel (19-point: the
+    # average of its two passes)
+    alg_per_launch = n ** 3 * ALG_BYTES[(var, prec)] / launches_per_step
     avg_launch_s = kms * 1e-3 / klaunch
     achieved = alg_per_launch / avg_launch_s / 1e9
-    traffic = load_traffic(tuned, a.layout)
+    traffic = load_traffic(tuned, a.layout, var, prec, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": f"substep55_sweep (fused RHS + RK3, {a.layout} layout)",
+                "kernel": (f"substep55_sweep (fused RHS + RK3, {a.layout} layout)" if var == "55p"
+                           else "substep19_pass1 / substep19_pass2 (average per launch)"),
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": klaunch,
                 "alg_bytes_per_launch": alg_per_launch,
                 "ghost_fill_us_per_launch": round(gms * 1e3 / max(glaunch, 1), 2),
@@ -323,39 +348,40 @@ def main():
 
     import oracle
     forms = {}
-    step_alg = ALG_BYTES[("55p", "fp32")]
-    forms["fp32"] = {"updates_per_s": value, "ms_per_step": ms_per_step,
-                     "hbm_frac_step": value * step_alg / (HBM_PEAK_GBS * 1e9)}
-    forms["fp32_graph"] = {"updates_per_s": n ** 3 * a.steps / (gev_ms * 1e-3),
+    step_alg = ALG_BYTES[(var, prec)]
+    hk = "fp32" if (prec, var) == ("fp32", "55p") else "headline"  # key of the headline form
+    forms[hk] = {"updates_per_s": value, "ms_per_step": ms_per_step,
+                 "hbm_frac_step": value * step_alg / (HBM_PEAK_GBS * 1e9)}
+    forms[f"{hk}_graph"] = {"updates_per_s": n ** 3 * a.steps / (gev_ms * 1e-3),
                            "ms_per_step": gev_ms / a.steps}
-    log(f"fp32 55p {n}^3 graph replay: {gev_ms / a.steps:.3f} ms/step")
+    log(f"{prec} {var} {n}^3 graph replay: {gev_ms / a.steps:.3f} ms/step")
     if not a.no_check:
-        forms["fp32"]["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields,
-                                                             "fp32", "55p", layout=a.layout)
+        forms[hk]["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields,
+                                                         prec, var, layout=a.layout)
     if not a.no_forms:
         k2 = max(5, a.steps // 5)
         other = "soa" if a.layout == "aos" else "aos"
-        for prec, var, lay in (("fp64", "55p", "aos"), ("fp64", "55p", "soa"),
-                               ("fp32_acc64", "55p", "aos"), ("fp32", "55p", other),
-                               ("fp32", "19p", "soa"), ("fp64", "19p", "soa")):
-            b2, tn = make_box(fd6, w, dev_fields, prec, var, layout=lay)
+        for fprec, fvar, lay in (("fp64", "55p", "aos"), ("fp64", "55p", "soa"),
+                                 ("fp32_acc64", "55p", "aos"), ("fp32", "55p", other),
+                                 ("fp32", "19p", "soa"), ("fp64", "19p", "soa")):
+            b2, tn = make_box(fd6, w, dev_fields, fprec, fvar, layout=lay)
             wl, em, tm = timed_steps(torch, b2, red, k2, 2)
             b2.close()
             v = n ** 3 * k2 / (em * 1e-3)
             entry = {"updates_per_s": v, "ms_per_step": em / k2,
-                     "hbm_frac_step": v * ALG_BYTES[(var, prec)] / (HBM_PEAK_GBS * 1e9),
+                     "hbm_frac_step": v * ALG_BYTES[(fvar, fprec)] / (HBM_PEAK_GBS * 1e9),
                      "speed_vs_fp64_55p": None}
             entry["kernel_shape"] = {"tile": tn["tile"], "zchunk": tn["zchunk"]}
             if not a.no_check:
-                entry["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields, prec,
-                                                             var, layout=lay)
-            key = f"{prec}_{var}" + (f"_{lay}" if var == "55p" else "")
+                entry["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields,
+                                                             fprec, fvar, layout=lay)
+            key = f"{fprec}_{fvar}" + (f"_{lay}" if fvar == "55p" else "")
             forms[key] = entry
             log(f"{key}: {em / k2:.3f} ms/step, {v / 1e9:.2f} G updates/s")
         base64 = forms["fp64_55p_aos"]["updates_per_s"]
-        forms["fp32"]["speed_vs_fp64_55p"] = value / base64
+        forms[hk]["speed_vs_fp64_55p"] = value / base64
         for k, e in forms.items():
-            if k != "fp32":
+            if k != hk:
                 e["speed_vs_fp64_55p"] = e["updates_per_s"] / base64
 
     if not a.no_forms:
@@ -393,12 +419,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE[prec],
         "data": "synthetic",
-        "config": {"workload": f"{n}^3 periodic box, FP32, 55-point fused substep, 16 random-phase "
+        "config": {"workload": f"{n}^3 periodic box, {PNAME[prec]}, {VNAME[var]}, 16 random-phase "
                                f"modes |k|<=16 A=0.1, nu=1e-3, cs=1, dt=0.4 CFL, FP64 reductions "
                                f"every step",
-                   "grid": [n, n, n], "precision": "fp32", "variant": "55p",
+                   "grid": [n, n, n], "precision": prec, "variant": var,
                    "layout": a.layout, "kernel_shape": tuned},
         "roofline": roofline,
         "cpu_baseline": cpu,
