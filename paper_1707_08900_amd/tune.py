@@ -6,7 +6,9 @@ keeps the fastest pair, and caches the choice in a JSON
 file keyed by grid shape, precision, variant, layout and device name (path from
 FD6_TUNE_CACHE, default ~/.cache/fd6_tune.json).  Tuning runs real steps, so
 it advances the box's state: call it before init_fields of the actual run,
-or re-initialise afterwards.
+or re-initialise afterwards.  The library's own tuner (fd6_tune, Box.tune)
+makes the same choice in C for callers without Python; this one also returns
+the timing of every candidate.
 """
 from __future__ import annotations
 
