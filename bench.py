@@ -278,9 +278,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the single-box kernel runs on one MI355X; see DESIGN.md for how it would "
-              "shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (a box runs on "
+              "one MI355X; splitting it into z slabs with a 3-plane halo exchange per substep "
+              "is not implemented). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
