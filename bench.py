@@ -53,7 +53,9 @@ def kernel_srcs(variant, precision):
     t = PREC_TAG[precision]
     files = ["sweep_common.hpp", "sweep_substep.hpp", f"substep55_{t}.hip"]
     files += [f"substep55_aos_{t}.hip"] if variant == "55p" else ["substep19.hip"]
-    return [os.path.join(ROOT, "paper_1707_08900_amd", "csrc", f) for f in files]
+    # build.py holds the compiler options, which shape the machine code too
+    return ([os.path.join(ROOT, "paper_1707_08900_amd", "csrc", f) for f in files] +
+            [os.path.join(ROOT, "paper_1707_08900_amd", "build.py")])
 
 
 def log(msg):

@@ -30,9 +30,22 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-ffp
           "-Wno-unused-command-line-argument", "-Wno-unknown-warning-option"]
 
 
+# Per-unit options.  The FP64 sweep kernels run at one wave per SIMD (they need
+# about 430 registers), so latency is hidden only by instruction-level
+# parallelism inside the wave: the scheduler's max-ILP strategy orders them for
+# that (512^3 AoS: 3640 -> 3525 us per launch; 32 x 8 with one array per field
+# 4268 -> 3742 us).  It slows the two-wave FP32 kernels (1462 -> 1583 us), so it
+# is applied to the FP64 units only.  Scheduling does not change results.
+UNIT_FLAGS = {
+    "substep55_f64.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "substep55_aos_f64.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
+
 def _compile(src: str, resource_usage: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, *UNIT_FLAGS.get(src, []), "-x", "hip", "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if resource_usage:
         cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
