@@ -11,7 +11,7 @@
  *
  * What it computes (paper section / equation):
  *   - ghost zone of R = 3 cells refreshed with periodic images
- *     (Sec. 4, opening paragraphs; "Compute boundary conditions" in Alg. 1-3)
+ *     (Sec. 4, opening paragraphs; the boundary step of Alg. 1-3)
  *   - first derivative, eq. (first_derivatives), Sec. 2.3
  *   - second derivative, eq. (second_derivatives), Sec. 2.3, with the
  *     prefactor read as 1/(180 dx^2) (the printed 1/(180 dx) is dimensionally
@@ -27,7 +27,10 @@
  *     does not print alpha/beta beyond alpha(1) = 0; the values used are the
  *     Williamson (1980) low-storage RK3 coefficients
  *     alpha = (0, -5/9, -153/128), beta = (1/3, 15/16, 8/15).
- *   - the 19-point two-pass variant, Algorithm 3 and Appendix A, Sec. 4.2
+ *   - the 19-point discretisation, Sec. 4.2 and Appendix A: grad div u as the
+ *     first derivative of the (ghost-filled) divergence field; Algorithm 3
+ *     splits its update into two passes, which in exact arithmetic equal the
+ *     single update done here (the tests check the split against it)
  *
  * Storage: a field is a ghosted array of (nx+6)(ny+6)(nz+6) doubles with x
  * fastest; interior point (i,j,k) lives at ((k+3)(ny+6) + (j+3))(nx+6) + i+3.
@@ -290,37 +293,31 @@ typedef struct {
     grid_t g;
     double *f[4]; /* ghosted lnrho, ux, uy, uz */
     double *w[4]; /* ghosted layout too (ghosts unused) */
-    double *o[4]; /* 19-point output arrays */
-    double *d;    /* 19-point divergence field */
+    double *r[4]; /* right-hand side (ghosts unused) */
+    double *d;    /* 19-point method: the divergence field, ghosted */
 } box_t;
 
 static void box_free(box_t *b) {
     for (int q = 0; q < 4; ++q) {
         free(b->f[q]);
         free(b->w[q]);
-        free(b->o[q]);
+        free(b->r[q]);
     }
     free(b->d);
 }
 
-static int box_alloc(box_t *b, int nx, int ny, int nz, int variant) {
+static int box_alloc(box_t *b, int nx, int ny, int nz) {
     memset(b, 0, sizeof(*b));
     b->g = make_grid(nx, ny, nz);
     size_t n = gsize(&b->g);
     for (int q = 0; q < 4; ++q) {
         b->f[q] = (double *)calloc(n, sizeof(double));
         b->w[q] = (double *)calloc(n, sizeof(double)); /* w = 0 at start */
-        if (!b->f[q] || !b->w[q]) return -1;
-        if (variant == VAR_19P) {
-            b->o[q] = (double *)calloc(n, sizeof(double));
-            if (!b->o[q]) return -1;
-        }
+        b->r[q] = (double *)calloc(n, sizeof(double));
+        if (!b->f[q] || !b->w[q] || !b->r[q]) return -1;
     }
-    if (variant == VAR_19P) {
-        b->d = (double *)calloc(n, sizeof(double));
-        if (!b->d) return -1;
-    }
-    return 0;
+    b->d = (double *)calloc(n, sizeof(double));
+    return b->d ? 0 : -1;
 }
 
 static state_view_t view_of(double *const f[4], const grid_t *g) {
@@ -341,42 +338,16 @@ static void set_threads(int nthreads) {
 #endif
 }
 
-/* One substep s (0-based) of Algorithm 1 for the 55-point method: boundary
- * conditions, then w <- alpha w + dt * d/dt(state) at every point, then
- * state <- state + beta w at every point. */
-static void substep55(box_t *b, const phys_t *p, double dt, int s) {
+/* Right-hand side d/dt (lnrho, u) of the periodic state b->f at every
+ * interior point, into b->r.  55-point method: rhs_point with the grad div u
+ * term of second and mixed derivatives.  19-point method (Sec. 4.2, Appendix
+ * A): rhs_point without it, plus (nu/3) D1_i of the divergence field
+ * d = D1 . u, whose ghost zone is filled with periodic images in between. */
+static void rhs_all(box_t *b, const phys_t *p, int variant) {
     grid_t *g = &b->g;
     for (int q = 0; q < 4; ++q) orc_fill_ghosts(g->nx, g->ny, g->nz, b->f[q]);
     state_view_t v = view_of(b->f, g);
-    const double a = RK_ALPHA[s], be = RK_BETA[s];
-#pragma omp parallel for schedule(static)
-    for (int k = 0; k < g->nz; ++k)
-        for (int j = 0; j < g->ny; ++j)
-            for (int i = 0; i < g->nx; ++i) {
-                size_t c = gidx(g, i, j, k);
-                const double xyz[3] = {i * p->h[0], j * p->h[1], k * p->h[2]};
-                double r[4];
-                rhs_point(&v, c, p, 1, xyz, r, NULL);
-                for (int q = 0; q < 4; ++q) b->w[q][c] = a * b->w[q][c] + dt * r[q];
-            }
-#pragma omp parallel for schedule(static)
-    for (int k = 0; k < g->nz; ++k)
-        for (int j = 0; j < g->ny; ++j)
-            for (int i = 0; i < g->nx; ++i) {
-                size_t c = gidx(g, i, j, k);
-                for (int q = 0; q < 4; ++q) b->f[q][c] = b->f[q][c] + be * b->w[q][c];
-            }
-}
-
-/* One substep s (0-based) of Algorithm 3, the 19-point method.  Pass 1: the
- * divergence field, the partial intermediate and output values.  Boundary
- * conditions on the divergence.  Pass 2: complete w and the output with
- * dt (nu/3) grad(div u).  Finally the output becomes the state. */
-static void substep19(box_t *b, const phys_t *p, double dt, int s) {
-    grid_t *g = &b->g;
-    for (int q = 0; q < 4; ++q) orc_fill_ghosts(g->nx, g->ny, g->nz, b->f[q]);
-    state_view_t v = view_of(b->f, g);
-    const double a = RK_ALPHA[s], be = RK_BETA[s];
+    const int full = variant == VAR_55P;
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < g->nz; ++k)
         for (int j = 0; j < g->ny; ++j)
@@ -384,31 +355,40 @@ static void substep19(box_t *b, const phys_t *p, double dt, int s) {
                 size_t c = gidx(g, i, j, k);
                 const double xyz[3] = {i * p->h[0], j * p->h[1], k * p->h[2]};
                 double r[4], div;
-                rhs_point(&v, c, p, 0, xyz, r, &div);
+                rhs_point(&v, c, p, full, xyz, r, &div);
                 b->d[c] = div;
-                for (int q = 0; q < 4; ++q) {
-                    b->w[q][c] = a * b->w[q][c] + dt * r[q];
-                    b->o[q][c] = b->f[q][c] + be * b->w[q][c];
-                }
+                for (int q = 0; q < 4; ++q) b->r[q][c] = r[q];
             }
+    if (full) return;
     orc_fill_ghosts(g->nx, g->ny, g->nz, b->d);
-    const double cgd = dt * (p->nu / 3.0);
+    const double nu3 = p->nu / 3.0;
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < g->nz; ++k)
         for (int j = 0; j < g->ny; ++j)
             for (int i = 0; i < g->nx; ++i) {
                 size_t c = gidx(g, i, j, k);
-                for (int q = 0; q < 3; ++q) {
-                    double t = cgd * op_d1(b->d, c, v.s[q], p->h[q]);
-                    b->w[1 + q][c] = b->w[1 + q][c] + t;
-                    b->o[1 + q][c] = b->o[1 + q][c] + be * t;
+                for (int q = 0; q < 3; ++q) b->r[1 + q][c] += nu3 * op_d1(b->d, c, v.s[q], p->h[q]);
+            }
+}
+
+/* One substep s (0-based) of the 2N-storage RK3, eq. (2N-RK_scheme): the
+ * right-hand side of the whole state first, then w <- alpha w + dt r and
+ * state <- state + beta w at every point (the order of Algorithm 1, which
+ * the in/out arrays of Algorithms 2 and 3 reproduce). */
+static void substep(box_t *b, const phys_t *p, double dt, int s, int variant) {
+    grid_t *g = &b->g;
+    rhs_all(b, p, variant);
+    const double a = RK_ALPHA[s], be = RK_BETA[s];
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < g->nz; ++k)
+        for (int j = 0; j < g->ny; ++j)
+            for (int i = 0; i < g->nx; ++i) {
+                size_t c = gidx(g, i, j, k);
+                for (int q = 0; q < 4; ++q) {
+                    b->w[q][c] = a * b->w[q][c] + dt * b->r[q][c];
+                    b->f[q][c] = b->f[q][c] + be * b->w[q][c];
                 }
             }
-    for (int q = 0; q < 4; ++q) { /* rho <- rho_out, u <- u_out */
-        double *t = b->f[q];
-        b->f[q] = b->o[q];
-        b->o[q] = t;
-    }
 }
 
 static int check_dims(int nx, int ny, int nz) {
@@ -416,8 +396,8 @@ static int check_dims(int nx, int ny, int nz) {
 }
 
 /* Advance the compact fields by nsteps full RK3 steps (three substeps each),
- * in place.  variant 0 = 55-point (Alg. 2 = Alg. 1 with separate arrays),
- * 1 = 19-point (Alg. 3).  w starts at zero. */
+ * in place.  variant 0 = 55-point, 1 = 19-point right-hand side.  w starts
+ * at zero. */
 int orc_rk3(int nx, int ny, int nz, double *lnrho, double *ux, double *uy, double *uz, double nu,
             double cs, double dx, double dy, double dz, double dt, int variant, int nsteps,
             int nthreads) {
@@ -425,7 +405,7 @@ int orc_rk3(int nx, int ny, int nz, double *lnrho, double *ux, double *uy, doubl
         return -1;
     set_threads(nthreads);
     box_t b;
-    if (box_alloc(&b, nx, ny, nz, variant)) {
+    if (box_alloc(&b, nx, ny, nz)) {
         box_free(&b);
         return -2;
     }
@@ -433,61 +413,30 @@ int orc_rk3(int nx, int ny, int nz, double *lnrho, double *ux, double *uy, doubl
     for (int q = 0; q < 4; ++q) orc_to_ghosted(nx, ny, nz, c[q], b.f[q]);
     phys_t p = {nu, cs, {dx, dy, dz}};
     for (int n = 0; n < nsteps; ++n)
-        for (int s = 0; s < 3; ++s) {
-            if (variant == VAR_55P)
-                substep55(&b, &p, dt, s);
-            else
-                substep19(&b, &p, dt, s);
-        }
+        for (int s = 0; s < 3; ++s) substep(&b, &p, dt, s, variant);
     for (int q = 0; q < 4; ++q) orc_from_ghosted(nx, ny, nz, b.f[q], c[q]);
     box_free(&b);
     return 0;
 }
 
-/* Right-hand side d/dt (lnrho, ux, uy, uz) of the current compact state.
- * variant 0: 55-point discretisation.  variant 1: 19-point discretisation,
- * i.e. the pass-1 terms plus (nu/3) D1_i(div u) with div u ghost-filled
- * (Appendix A). */
+/* Right-hand side d/dt (lnrho, ux, uy, uz) of the current compact state
+ * (variant as for orc_rk3). */
 int orc_rhs(int nx, int ny, int nz, const double *lnrho, const double *ux, const double *uy,
             const double *uz, double nu, double cs, double dx, double dy, double dz, int variant,
             double *r_lnrho, double *r_ux, double *r_uy, double *r_uz, int nthreads) {
     if (check_dims(nx, ny, nz) || (variant != VAR_55P && variant != VAR_19P)) return -1;
     set_threads(nthreads);
     box_t b;
-    if (box_alloc(&b, nx, ny, nz, variant)) {
+    if (box_alloc(&b, nx, ny, nz)) {
         box_free(&b);
         return -2;
     }
     const double *c[4] = {lnrho, ux, uy, uz};
     double *out[4] = {r_lnrho, r_ux, r_uy, r_uz};
-    grid_t *g = &b.g;
-    for (int q = 0; q < 4; ++q) {
-        orc_to_ghosted(nx, ny, nz, c[q], b.f[q]);
-        orc_fill_ghosts(nx, ny, nz, b.f[q]);
-    }
+    for (int q = 0; q < 4; ++q) orc_to_ghosted(nx, ny, nz, c[q], b.f[q]);
     phys_t p = {nu, cs, {dx, dy, dz}};
-    state_view_t v = view_of(b.f, g);
-#pragma omp parallel for schedule(static)
-    for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                size_t gc = gidx(g, i, j, k);
-                const double xyz[3] = {i * dx, j * dy, k * dz};
-                double r[4], div;
-                rhs_point(&v, gc, &p, variant == VAR_55P, xyz, r, &div);
-                if (variant == VAR_19P) b.d[gc] = div;
-                for (int q = 0; q < 4; ++q) out[q][cidx(g, i, j, k)] = r[q];
-            }
-    if (variant == VAR_19P) {
-        orc_fill_ghosts(nx, ny, nz, b.d);
-        for (int k = 0; k < nz; ++k)
-            for (int j = 0; j < ny; ++j)
-                for (int i = 0; i < nx; ++i) {
-                    size_t gc = gidx(g, i, j, k);
-                    for (int q = 0; q < 3; ++q)
-                        out[1 + q][cidx(g, i, j, k)] += (nu / 3.0) * op_d1(b.d, gc, v.s[q], p.h[q]);
-                }
-    }
+    rhs_all(&b, &p, variant);
+    for (int q = 0; q < 4; ++q) orc_from_ghosted(nx, ny, nz, b.r[q], out[q]);
     box_free(&b);
     return 0;
 }
@@ -496,7 +445,7 @@ int orc_rhs(int nx, int ny, int nz, const double *lnrho, const double *ux, const
 /* Local update of one point: the value after nsteps full steps at the       */
 /* centre of a cubic patch, without any boundary condition.  Each substep    */
 /* consumes R cells of the patch on every side (2R for the 19-point method,  */
-/* whose second pass differentiates the first pass's divergence), so a patch */
+/* whose grad div term differentiates the divergence field), so a patch      */
 /* of half-width m = nsteps * 3 * R (55p) or nsteps * 6 * R (19p) determines  */
 /* the centre exactly as the periodic run over the whole box does.  px, py,  */
 /* pz: coordinates of the patch points along each axis (for the force).      */
@@ -511,7 +460,7 @@ int orc_rk3_patch(int m, const double *lnrho, const double *ux, const double *uy
     if (nsteps < 1 || m < 3 * shrink * nsteps) return -1;
     const int n = 2 * m + 1;
     const size_t nn = (size_t)n * n * n;
-    double *f[4], *w[4], *o[4], *d;
+    double *f[4], *w[4], *r[4], *d;
     const double *in[4] = {lnrho, ux, uy, uz};
     int fail = 0;
     d = (double *)calloc(nn, sizeof(double));
@@ -519,8 +468,8 @@ int orc_rk3_patch(int m, const double *lnrho, const double *ux, const double *uy
     for (int q = 0; q < 4; ++q) {
         f[q] = (double *)malloc(nn * sizeof(double));
         w[q] = (double *)calloc(nn, sizeof(double));
-        o[q] = (double *)calloc(nn, sizeof(double));
-        if (!f[q] || !w[q] || !o[q]) fail = 1;
+        r[q] = (double *)calloc(nn, sizeof(double));
+        if (!f[q] || !w[q] || !r[q]) fail = 1;
         else memcpy(f[q], in[q], nn * sizeof(double));
     }
     if (!fail) {
@@ -529,61 +478,48 @@ int orc_rk3_patch(int m, const double *lnrho, const double *ux, const double *uy
         v.s[0] = 1;
         v.s[1] = n;
         v.s[2] = (ptrdiff_t)n * n;
+        const int full = variant == VAR_55P;
         int lo = 0; /* state is valid on [lo, n-lo)^3 */
         for (int step = 0; step < nsteps; ++step)
             for (int s = 0; s < 3; ++s) {
                 const double a = RK_ALPHA[s], be = RK_BETA[s];
                 v.lnrho = f[0];
                 for (int i = 0; i < 3; ++i) v.u[i] = f[1 + i];
-                if (variant == VAR_55P) {
-                    int a0 = lo + R, a1 = n - lo - R;
+                /* the terms of rhs_point (and the divergence) where R cells
+                 * of valid state surround the point */
+                int a0 = lo + R, a1 = n - lo - R;
+                for (int k = a0; k < a1; ++k)
+                    for (int j = a0; j < a1; ++j)
+                        for (int i = a0; i < a1; ++i) {
+                            size_t c = ((size_t)k * n + j) * n + i;
+                            const double xyz[3] = {px[i], py[j], pz[k]};
+                            double rp[4], div;
+                            rhs_point(&v, c, &p, full, xyz, rp, &div);
+                            d[c] = div;
+                            for (int q = 0; q < 4; ++q) r[q][c] = rp[q];
+                        }
+                if (!full) { /* (nu/3) D1_i d where R cells of d surround the point */
+                    a0 += R;
+                    a1 -= R;
+                    const double nu3 = nu / 3.0;
                     for (int k = a0; k < a1; ++k)
                         for (int j = a0; j < a1; ++j)
                             for (int i = a0; i < a1; ++i) {
                                 size_t c = ((size_t)k * n + j) * n + i;
-                                const double xyz[3] = {px[i], py[j], pz[k]};
-                                double r[4];
-                                rhs_point(&v, c, &p, 1, xyz, r, NULL);
-                                for (int q = 0; q < 4; ++q) {
-                                    w[q][c] = a * w[q][c] + dt * r[q];
-                                    o[q][c] = f[q][c] + be * w[q][c];
-                                }
+                                for (int q = 0; q < 3; ++q)
+                                    r[1 + q][c] += nu3 * op_d1(d, c, v.s[q], p.h[q]);
                             }
-                    lo += R;
-                } else {
-                    int a0 = lo + R, a1 = n - lo - R; /* pass 1 and the divergence */
-                    for (int k = a0; k < a1; ++k)
-                        for (int j = a0; j < a1; ++j)
-                            for (int i = a0; i < a1; ++i) {
-                                size_t c = ((size_t)k * n + j) * n + i;
-                                const double xyz[3] = {px[i], py[j], pz[k]};
-                                double r[4], div;
-                                rhs_point(&v, c, &p, 0, xyz, r, &div);
-                                d[c] = div;
-                                for (int q = 0; q < 4; ++q) {
-                                    w[q][c] = a * w[q][c] + dt * r[q];
-                                    o[q][c] = f[q][c] + be * w[q][c];
-                                }
-                            }
-                    const double cgd = dt * (nu / 3.0);
-                    int b0 = lo + 2 * R, b1 = n - lo - 2 * R; /* pass 2 */
-                    for (int k = b0; k < b1; ++k)
-                        for (int j = b0; j < b1; ++j)
-                            for (int i = b0; i < b1; ++i) {
-                                size_t c = ((size_t)k * n + j) * n + i;
-                                for (int q = 0; q < 3; ++q) {
-                                    double t = cgd * op_d1(d, c, v.s[q], p.h[q]);
-                                    w[1 + q][c] = w[1 + q][c] + t;
-                                    o[1 + q][c] = o[1 + q][c] + be * t;
-                                }
-                            }
-                    lo += 2 * R;
                 }
-                for (int q = 0; q < 4; ++q) {
-                    double *t = f[q];
-                    f[q] = o[q];
-                    o[q] = t;
-                }
+                for (int k = a0; k < a1; ++k)
+                    for (int j = a0; j < a1; ++j)
+                        for (int i = a0; i < a1; ++i) {
+                            size_t c = ((size_t)k * n + j) * n + i;
+                            for (int q = 0; q < 4; ++q) {
+                                w[q][c] = a * w[q][c] + dt * r[q][c];
+                                f[q][c] = f[q][c] + be * w[q][c];
+                            }
+                        }
+                lo += shrink;
             }
         size_t c = ((size_t)m * n + m) * n + m;
         for (int q = 0; q < 4; ++q) out[q] = f[q][c];
@@ -592,7 +528,7 @@ int orc_rk3_patch(int m, const double *lnrho, const double *ux, const double *uy
     for (int q = 0; q < 4; ++q) {
         free(f[q]);
         free(w[q]);
-        free(o[q]);
+        free(r[q]);
     }
     return fail ? -2 : 0;
 }

@@ -44,7 +44,9 @@ def dmix(f, a, b, ha, hb):
 
 
 def rhs(fields, nu, cs, h, variant="55p"):
-    """(d lnrho/dt, d u/dt) from eqs. continuity, navierstokes (f = 0), tensor."""
+    """(d lnrho/dt, d u/dt) from eqs. continuity, navierstokes (f = 0), tensor;
+    variant "55p" or "19p" (grad div u as D1 of D1 . u), or "no_graddiv"
+    (without the (nu/3) grad div u term)."""
     lnrho, *u = fields
     g = [d1(lnrho, j, h[j]) for j in range(3)]
     J = [[d1(u[i], j, h[j]) for j in range(3)] for i in range(3)]
@@ -53,6 +55,8 @@ def rhs(fields, nu, cs, h, variant="55p"):
     if variant == "19p":
         dfield = div
         gdiv = [d1(dfield, i, h[i]) for i in range(3)]
+    elif variant == "no_graddiv":  # the right-hand side of pass 1 of Algorithm 3
+        gdiv = [0.0, 0.0, 0.0]
     out = [r_lnrho]
     for i in range(3):
         adv = sum(u[j] * J[i][j] for j in range(3))
