@@ -1,19 +1,29 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the full RK3 step on one MI355X.
 
-Workload (the single-box FP32 throughput configuration): a 512^3 periodic
-box, FP32 storage and arithmetic, 55-point discretisation, fields lnrho and u
-as sums of 16 random-phase Fourier modes with |k| <= 16 and amplitude 0.1,
-nu = 1e-3, cs = 1, dt = 0.4 CFL, and FP64 global reductions (mass, kinetic
-energy, sum lnrho, max |u|, non-finite count) computed on the device after
-every step.  One step = 3 substeps, each one fused right-hand-side + 2N-RK3
-z-sweep kernel that resolves the periodic images in its loader; the third
-also produces the reductions' partials.  The state is stored as an array of
-structures (the four values of a point adjacent) unless --layout soa.
+Headline workload (the single-box FP32 throughput configuration): a 512^3
+periodic box, FP32 storage and arithmetic, 55-point discretisation, fields
+lnrho and u as sums of 16 random-phase Fourier modes with |k| <= 16 and
+amplitude 0.1, nu = 1e-3, cs = 1, dt = 0.4 CFL, and FP64 global reductions
+(mass, kinetic energy, sum lnrho, max |u|, non-finite count) computed on the
+device after every step.  One step = 3 substeps, each one fused
+right-hand-side + 2N-RK3 z-sweep kernel that resolves the periodic images in
+its loader; the third also produces the reductions' partials.  The state is
+stored as an array of structures (the four values of a point adjacent)
+unless --layout soa.  Kernel shape and z-chunk come from the library's
+autotuner.
+
+Beside it, on the same GPU ("forms"): the FP64 and FP32 + FP64-RK3-register
+precision forms, the other layout and the 19-point method at 512^3; the FP32
+step at 256^3 and the FP32 and FP64 steps at 768^3 (linear sound wave); the
+64-box ensemble in both layouts; the forced 19-point 256^3 run.  Every form
+states its error against the FP64 oracle on the same inputs: full fields
+after one step at 256^3 and 512^3 and for all 64 ensemble boxes, the wave's
+x-profile against the oracle's exact slab replica at 768^3.
 
 Prints ONE JSON line (metric, value in grid-point updates/s, roofline of the
 dominant kernel measured with HIP events on its stream, the FP64 oracle's
-rate on the host CPU, and the other precision forms on the same GPU).
+rate on the host CPU, and the forms).
 """
 from __future__ import annotations
 
@@ -36,6 +46,7 @@ HBM_PEAK_GBS = 8000.0
 # 19-point: 76 (28 to w).
 ALG_BYTES = {("55p", "fp32"): 160, ("55p", "fp64"): 320, ("55p", "fp32_acc64"): 224,
              ("19p", "fp32"): 304, ("19p", "fp64"): 608, ("19p", "fp32_acc64"): 416}
+LAUNCHES = {"55p": 3, "19p": 6}  # substep kernel launches per step
 PREC_TAG = {"fp32": "f32", "fp64": "f64", "fp32_acc64": "f32w64"}
 DTYPE = {"fp32": "f32", "fp64": "f64", "fp32_acc64": "f32 state, f64 RK3 register"}
 PNAME = {"fp32": "FP32", "fp64": "FP64", "fp32_acc64": "FP32 state with FP64 RK3 register"}
@@ -88,16 +99,64 @@ def load_traffic(shape, layout, variant="55p", precision="fp32", n=512):
     return t.get("traffic_bytes_per_launch")
 
 
-def make_box(fd6, w, dev_fields, precision, variant, tune=True, layout="soa"):
-    box = fd6.Box(w.shape, precision, variant, layout=layout)
-    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
-    tuned = None
-    if tune:
-        from paper_1707_08900_amd import tune as tuner
-        box.init_fields(dev_fields)
-        tuned = tuner.tune(box, steps=2, use_cache=False, reduce=True)
-    box.init_fields(dev_fields)
-    return box, tuned
+def device_copy(torch, nrep):
+    """A plain 1 GiB device-to-device copy, the streaming reference (and the
+    calibration kernel of the rocprofv3 traffic counters); GB/s read + write."""
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(nrep):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * src.numel() * 4 * nrep / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def cpu_threads():
+    """Host threads this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the host's share per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(n, 1)
+
+
+def host_cpu():
+    """(model name, physical cores, logical CPUs) of the host."""
+    model, cores = "unknown CPU", set()
+    try:
+        phys = core = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model == "unknown CPU":
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("physical id"):
+                    phys = line.split(":", 1)[1].strip()
+                elif line.startswith("core id"):
+                    core = line.split(":", 1)[1].strip()
+                elif not line.strip():
+                    if core is not None:
+                        cores.add((phys, core))
+                    phys = core = None
+    except OSError:
+        pass
+    return model, (len(cores) or None), os.cpu_count()
+
+
+def rel_errs(out, ref):
+    """Per field ||gpu - oracle||_inf / ||oracle||_inf."""
+    import numpy as np
+    return [float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+            for a, b in zip(out, ref)]
 
 
 def timed_steps(torch, box, red, steps, warmup, timing=True):
@@ -122,32 +181,89 @@ def timed_steps(torch, box, red, steps, warmup, timing=True):
     return wall, ev_ms, tm
 
 
-def sample_error(orc, fd6, si, w, dev_fields, precision, variant, nsamples=6, layout="soa"):
-    """Max over sampled points of |gpu - oracle| / max|field| after one step
-    from the workload's initial state (oracle on local patches)."""
-    import numpy as np
-    box, _ = make_box(fd6, w, dev_fields, precision, variant, tune=False, layout=layout)
-    box.step(1)
-    out = box.get_fields_device()
+def run_form(torch, fd6, w, dev_fields, prec, var, layout, steps, warmup, tile=None, zchunk=0,
+             graph=False, error_steps=1):
+    """Tune (or fix) the schedule, time `steps` reducing steps after `warmup`,
+    then run `error_steps` steps from the initial state in the same schedule
+    and return the state (FP64 device tensors) for the error check."""
+    from paper_1707_08900_amd import tune as tuner
+    n3 = int(w.shape[0]) * int(w.shape[1]) * int(w.shape[2])
+    box = fd6.Box(w.shape, prec, var, layout=layout)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(dev_fields)
+    if tile is None:
+        tuned = tuner.tune(box)
+    else:
+        box.set_tile(tile)
+        box.set_zchunk(zchunk)
+        tuned = {"tile": tile, "zchunk": zchunk}
+    box.init_fields(dev_fields)
+    red = torch.zeros(8, dtype=torch.float64, device="cuda")
+    wall, ev_ms, (kms, klaunch, gms, glaunch) = timed_steps(torch, box, red, steps, warmup)
+    v = n3 * steps / (ev_ms * 1e-3)
+    alg_launch = n3 * ALG_BYTES[(var, prec)] / LAUNCHES[var]
+    avg_launch_s = kms * 1e-3 / klaunch
+    res = {"updates_per_s": v, "ms_per_step": ev_ms / steps,
+           "hbm_frac_step": v * ALG_BYTES[(var, prec)] / (HBM_PEAK_GBS * 1e9),
+           "kernel_avg_launch_us": avg_launch_s * 1e6,
+           "kernel_hbm_frac": alg_launch / avg_launch_s / (HBM_PEAK_GBS * 1e9),
+           "kernel_shape": {"tile": tuned["tile"], "zchunk": tuned["zchunk"]},
+           "host_wall_ms_per_step": wall * 1e3 / steps,
+           "diagnostics": red[:5].cpu().tolist()}
+    extra = {"tuned": tuned, "kms": kms, "klaunch": klaunch, "gms": gms, "glaunch": glaunch}
+    if graph:
+        box.set_graph(True)
+        _, gev_ms, _ = timed_steps(torch, box, red, steps, 2, timing=False)
+        box.set_graph(False)
+        res["graph_ms_per_step"] = gev_ms / steps
+        res["graph_updates_per_s"] = n3 * steps / (gev_ms * 1e-3)
+    out = None
+    if error_steps > 0:
+        box.init_fields(dev_fields)
+        box.step_reduce(error_steps, red)
+        out = box.get_fields_device()
     box.close()
-    inp = si.as_float32_exact(w.fields) if precision != "fp64" else w.fields
-    rng = np.random.default_rng(123)
-    nz, ny, nx = w.shape
-    worst = 0.0
-    scale = [max(float(np.max(np.abs(f))), 1e-300) for f in inp]
-    for _ in range(nsamples):
-        c = (int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx)))
-        ref = orc.rk3_point(inp, c, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, variant, 1)
-        for q in range(4):
-            worst = max(worst, abs(float(out[q][c].item()) - ref[q]) / scale[q])
-    return worst
+    return res, extra, out
 
 
-def batch_form(torch, fd6, si, steps, layout="aos"):
+class OracleSteps:
+    """One-step FP64 oracle results of a workload, computed once per (method,
+    input precision): FP64 inputs, or the FP32-rounded inputs the FP32 forms
+    start from."""
+
+    def __init__(self, orc, si, w, threads):
+        self.orc, self.si, self.w, self.threads = orc, si, w, threads
+        self.cache, self.seconds = {}, {}
+
+    def get(self, var, prec):
+        key = (var, "fp64" if prec == "fp64" else "fp32")
+        if key not in self.cache:
+            w = self.w
+            inp = w.fields if key[1] == "fp64" else self.si.as_float32_exact(w.fields)
+            t0 = time.perf_counter()
+            self.cache[key] = self.orc.rk3(inp, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, var, 1,
+                                           self.threads)
+            self.seconds[key] = time.perf_counter() - t0
+            log(f"oracle step {key}: {self.seconds[key]:.2f} s on {self.threads} threads")
+        return self.cache[key]
+
+    def drop(self, var, prec):
+        self.cache.pop((var, "fp64" if prec == "fp64" else "fp32"), None)
+
+
+def with_error(res, out, ref):
+    e = rel_errs([t.cpu().numpy() for t in out], ref)
+    res["rel_err_1step"] = max(e)
+    res["rel_err_1step_fields"] = e
+    res["error_measure"] = "full fields after one step vs the FP64 oracle on the same inputs"
+
+
+def batch_form(torch, fd6, orc, si, steps, threads, layout="aos"):
     """64 independent boxes (edges from {32, 48, 64, 96}, per-box nu and
     amplitude, FP32), one persistent launch per substep, graph per step.
     The kernel shape and z-chunk are tuned on the ensemble itself by the
-    library's autotuner."""
+    library's autotuner; every box is then checked against the oracle after
+    one step."""
     import numpy as np
     members = si.ensemble(64)
     ws = [m.workload for m in members]
@@ -174,28 +290,42 @@ def batch_form(torch, fd6, si, steps, layout="aos"):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     red = b.reduce()
+    # error: every box after one step from its initial state
+    reinit()
+    b.step(1)
+    errs = []
+    for i, w in enumerate(ws):
+        ref = orc.rk3(si.as_float32_exact(w.fields), w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p",
+                      1, threads)
+        errs.append(max(rel_errs(b.get_fields(i), ref)))
     b.close()
+    by_edge = {}
+    for w, e in zip(ws, errs):
+        by_edge[str(w.shape[0])] = max(by_edge.get(str(w.shape[0]), 0.0), e)
     return {"updates_per_s": pts / (ms * 1e-3), "ms_per_step": ms, "boxes": len(ws),
             "points": pts, "sizes": sorted(set(w.shape[0] for w in ws)),
             "schedule": {"tile": best[0], "zchunk": best[1]},
             "tuning_s": round(tune_s, 2),
             "hbm_frac_step": pts / (ms * 1e-3) * ALG_BYTES[("55p", "fp32")] / (HBM_PEAK_GBS * 1e9),
-            "all_finite": all(r["nonfinite"] == 0 for r in red)}
+            "all_finite": all(r["nonfinite"] == 0 for r in red),
+            "rel_err_1step": max(errs), "rel_err_1step_by_edge": by_edge,
+            "error_measure": "all 64 boxes, full fields after one step vs the FP64 oracle on "
+                             "the same FP32-rounded inputs"}
 
 
 def forced_form(torch, fd6, si, steps):
     """The forced-turbulence configuration of Sec. 6: 19-point method, 256^3,
     nu = 1.4e-4, FP32, a new forcing mode drawn every step (isotropic shell
     1 <= |k| <= 3, f0 = 0.02), next to the same steps without the force."""
+    from paper_1707_08900_amd import tune as tuner
     n = 256
     w = si.fourier_box(n, seed=0, amplitude=0.1, kmax=16.0, nu=1.4e-4)
     draws = si.forcing_draws(steps + 2, 1.0, 3.0, 0.02, seed=0)
     dev = [torch.from_numpy(f).cuda() for f in w.fields]
     box = fd6.Box(w.shape, "fp32", "19p")
     box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
-    from paper_1707_08900_amd import tune as tuner
     box.init_fields(dev)
-    tuned = tuner.tune(box, steps=2, use_cache=False)
+    tuned = tuner.tune(box)
     res = {}
     for forced in (True, False):
         box.init_fields(dev)
@@ -219,35 +349,68 @@ def forced_form(torch, fd6, si, steps):
                         "1 <= |k| <= 3, f0 = 0.02"}
 
 
-def cpu_baseline(orc, si, w, threads):
-    """FP64 oracle rate on a bounded sample of the workload: one full RK3
-    step of the whole box on the host threads, and one step of its first 48
-    z-planes (as a periodic box) on one thread; about 10-15 s in all."""
-    warm = [f[:8].copy() for f in w.fields]
-    orc.rk3(warm, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, threads)  # load, thread pool
+SOUND_A, SOUND_K = 1e-4, 4
+
+
+def sound_form(torch, fd6, orc, si, n, prec, steps, warmup, err_steps, threads):
+    """The 768^3 linear sound wave (lnrho = 1e-4 sin(4x), u = 0, nu = 1e-4,
+    dt = 0.4 dx): step rate, and after err_steps steps the x-profile against
+    the oracle's exact n x 8 x 8 slab replica (the fields never vary in y
+    and z) plus the spread across columns."""
+    slab = si.sound_wave_box(shape=(8, 8, n), amplitude=SOUND_A, k=SOUND_K)
+    h = 2 * math.pi / n
+
+    class W:  # the n^3 box with the slab's parameters
+        shape, nu, cs, dx, dy, dz, dt = (n, n, n), slab.nu, slab.cs, h, h, h, slab.dt
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * h
+    lnrho = (SOUND_A * torch.sin(SOUND_K * x)).expand(n, n, n).contiguous()
+    zero = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    dev = [lnrho, zero, zero, zero]
+    res, extra, out = run_form(torch, fd6, W, dev, prec, "55p", "aos", steps, warmup,
+                               error_steps=err_steps)
+    del dev, lnrho, zero
+    lr, ux = out[0], out[1]
+    spread = float((lr - lr[0:1, 0:1, :]).abs().max()) / SOUND_A
+    prof = [lr[0, 0].cpu().numpy(), ux[0, 0].cpu().numpy()]
+    del out, lr, ux
+    torch.cuda.empty_cache()
+    f = slab.fields if prec == "fp64" else si.as_float32_exact(slab.fields)
+    ref = orc.rk3(f, slab.nu, slab.cs, h, h, h, slab.dt, "55p", err_steps, threads)
+    import numpy as np
+    e = max(float(np.max(np.abs(prof[0] - ref[0][0, 0]))),
+            float(np.max(np.abs(prof[1] - ref[1][0, 0])))) / SOUND_A
+    res.update({"rel_err_profile": e, "column_spread": spread, "error_steps": err_steps,
+                "error_measure": f"x-profiles of lnrho and ux after {err_steps} steps vs the "
+                                 f"oracle's exact {n}x8x8 slab replica, relative to the "
+                                 f"amplitude 1e-4",
+                "workload": f"{n}^3 linear sound wave, lnrho = 1e-4 sin(4x), u = 0, nu = 1e-4, "
+                            f"dt = 0.4 dx"})
+    return res, extra
+
+
+def cpu_baseline(orefs, w, threads, oracle_key):
+    """FP64 oracle rate: one full RK3 step of the whole workload on the host
+    threads (the step the GPU forms are checked against), and one step of its
+    first 48 z-planes (as a periodic box) on one thread."""
+    orc, si = orefs.orc, orefs.si
+    orefs.get(*oracle_key)
+    dt = orefs.seconds[(oracle_key[0], "fp64" if oracle_key[1] == "fp64" else "fp32")]
     nzs = w.shape[0]
-    t0 = time.perf_counter()
-    orc.rk3(w.fields, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, threads)
-    dt = time.perf_counter() - t0
     pts = nzs * w.shape[1] * w.shape[2]
-    # the same oracle on one core
     nz1 = min(48, nzs)
     s1 = [f[:nz1].copy() for f in w.fields]
     t0 = time.perf_counter()
     orc.rk3(s1, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, 1)
     dt1 = time.perf_counter() - t0
-    cpu = "unknown CPU"
-    try:
-        with open("/proc/cpuinfo") as f:
-            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
+    model, phys, logical = host_cpu()
     return {"value": pts / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "value_1core": nz1 * w.shape[1] * w.shape[2] / dt1,
+            "host_cpu": model, "host_physical_cores": phys, "host_logical_cpus": logical,
             "sample": f"the whole {w.shape[2]}x{w.shape[1]}x{nzs} workload, one RK3 step, FP64 "
-                      f"C oracle with {threads} OpenMP threads ({dt:.2f} s); value_1core: its "
-                      f"first {nz1} z-planes as a periodic box on 1 thread ({dt1:.2f} s); "
-                      f"host CPU: {cpu}"}
+                      f"C oracle with {threads} OpenMP threads, all the host threads this "
+                      f"process may use ({dt:.2f} s); value_1core: its first {nz1} z-planes as "
+                      f"a periodic box on 1 thread ({dt1:.2f} s); host CPU: {model}, "
+                      f"{phys} physical cores, {logical} logical CPUs"}
 
 
 def main():
@@ -256,10 +419,13 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP64/ACC64/19p forms")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other precision, layout, method and size forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle error checks")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble form")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched ensemble (AoS) and print its entry (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for rocprofv3)")
     ap.add_argument("--tile", type=int, default=None,
@@ -276,7 +442,6 @@ def main():
     if a.variant == "19p":
         a.layout = "soa"  # the 19-point passes keep one array per field
     prec, var = a.precision, a.variant
-    launches_per_step = 3 if var == "55p" else 6
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -285,57 +450,47 @@ def main():
               "is not implemented). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import paper_1707_08900_amd as fd6
     import synthetic_inputs as si
+    threads = cpu_threads()
+
+    if a.batch_only:
+        import oracle
+        oracle.build(force=False)
+        if a.calibrate_copy:
+            log(f"device copy 1 GiB: {device_copy(torch, 3):.0f} GB/s (read + write)")
+        bf = batch_form(torch, fd6, oracle, si, a.steps, threads, layout="aos")
+        log(f"batched aos: {bf['ms_per_step']:.3f} ms/step, {bf['updates_per_s'] / 1e9:.2f} G "
+            f"updates/s, schedule {bf['schedule']}, rel err {bf['rel_err_1step']:.3e}")
+        print(json.dumps({"metric": "batched grid-point updates/s", "value": bf["updates_per_s"],
+                          "unit": "updates/s", "batched_fp32": bf}), flush=True)
+        return
 
     n = a.size
     t0 = time.perf_counter()
     w = si.large_box(n)
     log(f"inputs {n}^3 generated in {time.perf_counter() - t0:.1f} s; dt = {w.dt:.4e}")
 
-    # streaming reference: a plain 1 GiB device-to-device copy (also the
-    # calibration kernel of the rocprofv3 traffic counters)
-    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(3 if a.calibrate_copy else 5):
-        dst.copy_(src)
-    e1.record()
-    e1.synchronize()
-    copy_gbs = 2 * src.numel() * 4 * (3 if a.calibrate_copy else 5) / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
+    copy_gbs = device_copy(torch, 3 if a.calibrate_copy else 5)
     log(f"device copy 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
 
     dev_fields = [torch.from_numpy(f).cuda() for f in w.fields]
-    red = torch.zeros(8, dtype=torch.float64, device="cuda")
-    box, tuned = make_box(fd6, w, dev_fields, prec, var, tune=a.tile is None,
-                          layout=a.layout)
-    if a.tile is not None:
-        box.set_tile(a.tile)
-        box.set_zchunk(a.zchunk)
-        tuned = {"tile": a.tile, "zchunk": a.zchunk}
+    hk = "fp32" if (prec, var, n) == ("fp32", "55p", 512) else "headline"
+    head, hx, hout = run_form(torch, fd6, w, dev_fields, prec, var, a.layout, a.steps, a.warmup,
+                              tile=a.tile, zchunk=a.zchunk, graph=True,
+                              error_steps=0 if a.no_check else 1)
+    tuned = hx["tuned"]
     log(f"kernel shape: {tuned}")
-    wall, ev_ms, (kms, klaunch, gms, glaunch) = timed_steps(torch, box, red, a.steps, a.warmup)
-    r = red.cpu().numpy()
-    # the same steps replayed from a captured graph per step (no per-launch
-    # events in this mode)
-    box.set_graph(True)
-    _, gev_ms, _ = timed_steps(torch, box, red, a.steps, 2, timing=False)
-    box.set_graph(False)
-    box.close()
-    ms_per_step = ev_ms / a.steps
-    value = n ** 3 * a.steps / (ev_ms * 1e-3)
-    log(f"{prec} {var} {a.layout} {n}^3: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} G updates/s "
-        f"(host wall {wall * 1e3 / a.steps:.3f} ms/step); mass {r[0]:.10e} ke {r[1]:.6e}")
+    ms_per_step = head["ms_per_step"]
+    value = head["updates_per_s"]
+    log(f"{prec} {var} {a.layout} {n}^3: {ms_per_step:.3f} ms/step, {value / 1e9:.2f} G updates/s; "
+        f"graph replay {head['graph_ms_per_step']:.3f} ms/step")
 
     # dominant kernel: the fused 55-point substep kernel (19-point: the
     # average of its two passes)
-    alg_per_launch = n ** 3 * ALG_BYTES[(var, prec)] / launches_per_step
-    avg_launch_s = kms * 1e-3 / klaunch
+    alg_per_launch = n ** 3 * ALG_BYTES[(var, prec)] / LAUNCHES[var]
+    avg_launch_s = hx["kms"] * 1e-3 / hx["klaunch"]
     achieved = alg_per_launch / avg_launch_s / 1e9
     traffic = load_traffic(tuned, a.layout, var, prec, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -343,48 +498,82 @@ def main():
                 "traffic": traffic,
                 "kernel": (f"substep55_sweep (fused RHS + RK3, {a.layout} layout)" if var == "55p"
                            else "substep19_pass1 / substep19_pass2 (average per launch)"),
-                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": klaunch,
+                "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": hx["klaunch"],
                 "alg_bytes_per_launch": alg_per_launch,
-                "ghost_fill_us_per_launch": round(gms * 1e3 / max(glaunch, 1), 2),
+                "ghost_fill_us_per_launch": round(hx["gms"] * 1e3 / max(hx["glaunch"], 1), 2),
                 "device_copy_gbs": round(copy_gbs, 1)}
 
     import oracle
-    forms = {}
-    step_alg = ALG_BYTES[(var, prec)]
-    hk = "fp32" if (prec, var) == ("fp32", "55p") else "headline"  # key of the headline form
-    forms[hk] = {"updates_per_s": value, "ms_per_step": ms_per_step,
-                 "hbm_frac_step": value * step_alg / (HBM_PEAK_GBS * 1e9)}
-    forms[f"{hk}_graph"] = {"updates_per_s": n ** 3 * a.steps / (gev_ms * 1e-3),
-                           "ms_per_step": gev_ms / a.steps}
-    log(f"{prec} {var} {n}^3 graph replay: {gev_ms / a.steps:.3f} ms/step")
+    oracle.build(force=False)
+    orefs = OracleSteps(oracle, si, w, threads)
+    forms = {hk: head}
     if not a.no_check:
-        forms[hk]["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields,
-                                                         prec, var, layout=a.layout)
+        with_error(head, hout, orefs.get(var, prec))
+        log(f"headline rel err after one step (full fields): {head['rel_err_1step']:.3e}")
+    del hout
+    cpu = None
+    if not a.no_cpu_baseline:
+        cpu = cpu_baseline(orefs, w, threads, (var, prec))
+        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M updates/s on {threads} threads")
+
     if not a.no_forms:
-        k2 = max(5, a.steps // 5)
         other = "soa" if a.layout == "aos" else "aos"
-        for fprec, fvar, lay in (("fp64", "55p", "aos"), ("fp64", "55p", "soa"),
-                                 ("fp32_acc64", "55p", "aos"), ("fp32", "55p", other),
-                                 ("fp32", "19p", "soa"), ("fp64", "19p", "soa")):
-            b2, tn = make_box(fd6, w, dev_fields, fprec, fvar, layout=lay)
-            wl, em, tm = timed_steps(torch, b2, red, k2, 2)
-            b2.close()
-            v = n ** 3 * k2 / (em * 1e-3)
-            entry = {"updates_per_s": v, "ms_per_step": em / k2,
-                     "hbm_frac_step": v * ALG_BYTES[(fvar, fprec)] / (HBM_PEAK_GBS * 1e9),
-                     "speed_vs_fp64_55p": None}
-            entry["kernel_shape"] = {"tile": tn["tile"], "zchunk": tn["zchunk"]}
+        # grouped by the oracle step they are checked against
+        plan = [("fp32", "55p", other), ("fp32_acc64", "55p", "aos"),
+                ("fp64", "55p", "aos"), ("fp64", "55p", "soa"),
+                ("fp32", "19p", "soa"), ("fp64", "19p", "soa")]
+        for i, (fprec, fvar, lay) in enumerate(plan):
+            if (fprec, fvar, lay) == (prec, var, a.layout):
+                continue
+            entry, _, out = run_form(torch, fd6, w, dev_fields, fprec, fvar, lay, a.steps, 2,
+                                     error_steps=0 if a.no_check else 1)
             if not a.no_check:
-                entry["sample_rel_err_1step"] = sample_error(oracle, fd6, si, w, dev_fields,
-                                                             fprec, fvar, layout=lay)
+                with_error(entry, out, orefs.get(fvar, fprec))
+            del out
             key = f"{fprec}_{fvar}" + (f"_{lay}" if fvar == "55p" else "")
             forms[key] = entry
-            log(f"{key}: {em / k2:.3f} ms/step, {v / 1e9:.2f} G updates/s")
-        base64 = forms["fp64_55p_aos"]["updates_per_s"]
-        forms[hk]["speed_vs_fp64_55p"] = value / base64
-        for k, e in forms.items():
-            if k != hk:
+            log(f"{key}: {entry['ms_per_step']:.3f} ms/step, "
+                f"{entry['updates_per_s'] / 1e9:.2f} G updates/s, "
+                f"rel err {entry.get('rel_err_1step', float('nan')):.3e}")
+            # free an oracle step once no later form is checked against it
+            okey = (fvar, fprec == "fp64")
+            if all((v2, p2 == "fp64") != okey for p2, v2, _ in plan[i + 1:]):
+                orefs.drop(fvar, fprec)
+        orefs.cache.clear()
+        base64 = forms.get("fp64_55p_aos", {}).get("updates_per_s")
+        if base64:
+            for k, e in forms.items():
                 e["speed_vs_fp64_55p"] = e["updates_per_s"] / base64
+    del dev_fields
+    torch.cuda.empty_cache()
+
+    if not a.no_forms and n == 512:
+        # the size sweep: 256^3 (random-phase, full-field error) and 768^3
+        # (the linear sound wave, profile error), FP32 and FP64 at 768^3
+        w256 = si.large_box(256)
+        d256 = [torch.from_numpy(f).cuda() for f in w256.fields]
+        e256, _, out = run_form(torch, fd6, w256, d256, "fp32", "55p", "aos", a.steps, 2,
+                                error_steps=0 if a.no_check else 1)
+        if not a.no_check:
+            o256 = OracleSteps(oracle, si, w256, threads)
+            with_error(e256, out, o256.get("55p", "fp32"))
+        e256["workload"] = "256^3 random-phase |k|<=16 A=0.1, nu=1e-3"
+        forms["fp32_55p_aos_256"] = e256
+        del out, d256
+        log(f"fp32 256^3: {e256['ms_per_step']:.3f} ms/step, "
+            f"{e256['updates_per_s'] / 1e9:.2f} G updates/s, kernel "
+            f"{e256['kernel_hbm_frac']:.3f} of HBM peak")
+        for sprec in ("fp32", "fp64"):
+            e768, _ = sound_form(torch, fd6, oracle, si, 768, sprec, a.steps, 2,
+                                 0 if a.no_check else 100, threads)
+            forms[f"{sprec}_55p_aos_768"] = e768
+            log(f"{sprec} 768^3: {e768['ms_per_step']:.3f} ms/step, "
+                f"{e768['updates_per_s'] / 1e9:.2f} G updates/s, kernel "
+                f"{e768['kernel_hbm_frac']:.3f} of HBM peak, profile err "
+                f"{e768.get('rel_err_profile', float('nan')):.3e}")
+            torch.cuda.empty_cache()
+        f32, f64 = forms["fp32_55p_aos_768"], forms["fp64_55p_aos_768"]
+        f32["speed_vs_fp64_768"] = f32["updates_per_s"] / f64["updates_per_s"]
 
     if not a.no_forms:
         forms["forced_fp32_19p_256"] = forced_form(torch, fd6, si, max(10, a.steps // 2))
@@ -394,21 +583,15 @@ def main():
 
     if not a.no_batch:
         for lay, key in (("aos", "batched_fp32"), ("soa", "batched_fp32_soa")):
-            forms[key] = batch_form(torch, fd6, si, max(10, a.steps // 2), layout=lay)
+            forms[key] = batch_form(torch, fd6, oracle, si, a.steps, threads, layout=lay)
             bf = forms[key]
             log(f"batched {lay}: {bf['ms_per_step']:.3f} ms/step, "
                 f"{bf['updates_per_s'] / 1e9:.2f} G updates/s ({bf['boxes']} boxes, "
-                f"{bf['points']} points, schedule {bf['schedule']})")
+                f"{bf['points']} points, schedule {bf['schedule']}), "
+                f"rel err {bf['rel_err_1step']:.3e}")
             if "fp64_55p_aos" in forms:
                 bf["speed_vs_fp64_55p"] = (bf["updates_per_s"] /
                                            forms["fp64_55p_aos"]["updates_per_s"])
-
-    cpu = None
-    if not a.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        oracle.build(force=False)
-        cpu = cpu_baseline(oracle, si, w, threads)
-        log(f"cpu oracle: {cpu['value'] / 1e6:.2f} M updates/s on {threads} threads")
 
     out = {
         "metric": "grid-point updates/s per full RK3 step + % HBM roofline (FP64 vs FP32 vs batched)",
@@ -427,11 +610,13 @@ def main():
                                f"modes |k|<=16 A=0.1, nu=1e-3, cs=1, dt=0.4 CFL, FP64 reductions "
                                f"every step",
                    "grid": [n, n, n], "precision": prec, "variant": var,
-                   "layout": a.layout, "kernel_shape": tuned},
+                   "layout": a.layout, "kernel_shape": {"tile": tuned["tile"],
+                                                        "zchunk": tuned["zchunk"]}},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms,
-        "hbm_frac_step": value * step_alg / (HBM_PEAK_GBS * 1e9),
+        "hbm_frac_step": value * ALG_BYTES[(var, prec)] / (HBM_PEAK_GBS * 1e9),
+        "rel_err_1step": head.get("rel_err_1step"),
     }
     print(json.dumps(out), flush=True)
 

@@ -95,7 +95,9 @@ typedef struct {
 
 /* FP64 global diagnostics of the state: mass = dV sum exp(lnrho), kinetic
  * energy = dV sum exp(lnrho)|u|^2/2, sum of lnrho, max |u|, and the number
- * of grid points holding a non-finite value in any field. */
+ * of grid points holding a non-finite value in any field.  When that number
+ * is not zero, mass and kinetic energy are NaN.  Sums are in FP64 in a fixed
+ * order (bitwise reproducible); exp is evaluated to within 2 ulp. */
 typedef struct {
     double mass, kinetic_energy, sum_lnrho, umax;
     int64_t nonfinite;
@@ -207,6 +209,15 @@ int fd6_get_schedule(const fd6_box *box, int32_t *tile, int32_t *zchunk);
  * are set.  Synchronises. */
 int fd6_tune(fd6_box *box, const char *cache_path);
 
+/* The candidates the box's last fd6_tune call timed, in order: kernel shape,
+ * z-chunk length and milliseconds per step (the mean of its timed steps).
+ * Fills min(cap, count) entries of the three arrays and sets *n = count (0
+ * when the last call took a cached choice or no call was made).  cap = 0
+ * with NULL arrays queries the count.  FD6_EINVAL for null handle or n,
+ * cap < 0, or cap > 0 with a null array. */
+int fd6_get_tune_log(const fd6_box *box, int32_t *tiles, int32_t *zchunks, float *ms,
+                     int32_t cap, int32_t *n);
+
 /* External force of the momentum equation: one Fourier mode of eq.
  * (forcing), Sec. 6,
  *   f(x) = Re{ N f_k exp(i k.x + i phase) },  N = f0 cs sqrt(|k| cs / dt),
@@ -285,9 +296,13 @@ int fd6_batch_init_fields(fd6_batch *batch, int32_t box, const double *lnrho, co
 
 /* Kernel shape (1 .. fd6_tile_count()-1, a z-sweep shape) and z-chunk length
  * of the work items: each box's z range is split evenly into chunks of at
- * most zchunk planes (0 = whole boxes).  Rebuilds the work list and drops any
- * captured graph.  Default: shape 8 (32 x 8, two planes ahead), chunks of at
- * most 64 planes. */
+ * most zchunk planes (0 = whole boxes; otherwise zchunk >= 8, since every
+ * chunk re-reads 6 planes).  Rebuilds the work list and drops any captured
+ * graph.  FD6_EINVAL for a shape out of range or 0 < zchunk < 8;
+ * FD6_EUNSUPPORTED for a shape the ensemble's layout does not take.  A
+ * refused call leaves the schedule in force (and fd6_batch_get_schedule's
+ * answer) unchanged.  Default: shape 8 (32 x 8, two planes ahead), chunks of
+ * at most 64 planes. */
 int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
 
 /* Autotuner of the ensemble schedule (the shape and chunk choice is the
@@ -300,7 +315,8 @@ int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
  * "key tile zchunk" lines, keyed by device name, precision, layout and box
  * shapes: a cached entry is applied without timing, a new result is appended
  * (a file that cannot be opened is ignored).  FD6_ESTATE before parameters
- * and fields are set.  Synchronises. */
+ * and fields are set.  If a trial fails, the schedule in force before the
+ * call is restored and the failure returned.  Synchronises. */
 int fd6_batch_tune(fd6_batch *batch, const char *cache_path);
 
 /* The current schedule (set or tuned). */

@@ -38,7 +38,7 @@ ABI_SYMBOLS = (
     "fd6_set_stream", "fd6_set_params", "fd6_init_fields", "fd6_init_fields_device",
     "fd6_rk3_step", "fd6_rk3_step_reduce", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
     "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_zchunk", "fd6_set_graph",
-    "fd6_get_schedule", "fd6_tune",
+    "fd6_get_schedule", "fd6_tune", "fd6_get_tune_log",
     "fd6_set_forcing", "fd6_set_timing",
     "fd6_get_timing",
     "fd6_last_error", "fd6_batch_workspace_bytes", "fd6_batch_create", "fd6_batch_destroy",
@@ -116,6 +116,10 @@ def _declare(lib):
         "fd6_batch_set_schedule": (I, [P, ctypes.c_int32, ctypes.c_int32]),
         "fd6_tune": (I, [P, ctypes.c_char_p]),
         "fd6_get_schedule": (I, [P, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32)]),
+        "fd6_get_tune_log": (I, [P, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                  ctypes.POINTER(ctypes.c_int32)]),
         "fd6_batch_tune": (I, [P, ctypes.c_char_p]),
         "fd6_batch_get_schedule": (I, [P, ctypes.POINTER(ctypes.c_int32),
@@ -303,11 +307,22 @@ class Box:
 
     def tune(self, cache_path: Optional[str] = None):
         """The library's autotuner (fd6_tune; advances the state, so set the
-        fields again afterwards).  Returns (tile, zchunk).  tune.tune() is the
-        Python tuner with per-candidate timings."""
+        fields again afterwards).  Returns (tile, zchunk); tune_log() lists
+        the candidates it timed."""
         path = cache_path.encode() if cache_path else None
         self._check(self.lib.fd6_tune(self.h, path), "fd6_tune")
         return self.get_schedule()
+
+    def tune_log(self):
+        """[(tile, zchunk, ms per step)] timed by the last tune() call."""
+        n = ctypes.c_int32()
+        self._check(self.lib.fd6_get_tune_log(self.h, None, None, None, 0, ctypes.byref(n)),
+                    "fd6_get_tune_log")
+        k = n.value
+        t, z, m = (ctypes.c_int32 * k)(), (ctypes.c_int32 * k)(), (ctypes.c_float * k)()
+        self._check(self.lib.fd6_get_tune_log(self.h, t, z, m, k, ctypes.byref(n)),
+                    "fd6_get_tune_log")
+        return [(t[i], z[i], float(m[i])) for i in range(k)]
 
     def set_forcing(self, forcing=None):
         """External force (one mode of eq. forcing) for the following steps:
@@ -425,3 +440,4 @@ class Batch:
 
 def tile_count() -> int:
     return library().fd6_tile_count()
+

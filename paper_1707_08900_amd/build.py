@@ -42,8 +42,24 @@ UNIT_FLAGS = {
 }
 
 
-def _compile(src: str, resource_usage: bool) -> str:
+def _up_to_date(src: str, obj: str) -> bool:
+    """The object is newer than its source, every header of the library and
+    this file (which holds the compiler options)."""
+    if not os.path.exists(obj):
+        return False
+    t = os.path.getmtime(obj)
+    deps = [os.path.join(CSRC, src), os.path.abspath(__file__)]
+    with open(deps[0]) as f:
+        if "fd6.h" in f.read():
+            deps.append(os.path.join(HERE, "..", "include", "fd6.h"))
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    return all(os.path.getmtime(d) < t for d in deps)
+
+
+def _compile(src: str, resource_usage: bool, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and not resource_usage and _up_to_date(src, obj):
+        return obj
     cmd = [HIPCC, *COMMON, *UNIT_FLAGS.get(src, []), "-x", "hip", "-c",
            os.path.join(CSRC, src), "-o", obj]
     if resource_usage:
@@ -56,11 +72,13 @@ def _compile(src: str, resource_usage: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, resource_usage: bool = False) -> str:
+def build(verbose: bool = False, resource_usage: bool = False, incremental: bool = False) -> str:
+    """Compile every unit (incremental: only units older than their source, a
+    header or this file) and link libfd6.so."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, resource_usage), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, resource_usage, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -76,5 +94,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--resource-usage", action="store_true")
+    ap.add_argument("--incremental", action="store_true",
+                    help="skip units whose object is newer than every source and header")
     a = ap.parse_args()
-    build(verbose=True, resource_usage=a.resource_usage)
+    build(verbose=True, resource_usage=a.resource_usage, incremental=a.incremental)

@@ -1,5 +1,6 @@
 // Auxiliary kernels: periodic ghost fill, FP64 import/export of the state,
 // and the deterministic FP64 global reductions.
+#include "exp_fp64.hpp"
 #include "fd6_internal.hpp"
 
 namespace fd6 {
@@ -7,8 +8,8 @@ namespace {
 
 __device__ inline int wrap_index(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Periodic boundary condition of Sec. 4 ("Compute boundary conditions" in
-// Algorithms 1-3): every ghost cell (i, j, k) in [-3, n+3)^3 \ [0, n)^3 takes
+// Periodic boundary condition of Sec. 4 (the boundary step of Algorithms
+// 1-3): every ghost cell (i, j, k) in [-3, n+3)^3 \ [0, n)^3 takes
 // the value of its periodic image (i mod nx, j mod ny, k mod nz).  The image
 // is always an interior cell (n >= 6 > R), so all ghost cells are independent.
 // The ghost cells are enumerated region by region so that consecutive threads
@@ -160,10 +161,11 @@ __global__ __launch_bounds__(kRedThreads) void reduce_partials_kernel(Geom g, Fi
             const long long c = (base + i) * g.vs;
             const double lr = (double)f.f[0][c], ux = (double)f.f[1][c], uy = (double)f.f[2][c],
                          uz = (double)f.f[3][c];
-            const double rho = exp(lr);
+            // the per-point quantities of the fused diagnostics (red_point)
+            const double rho = exp_fp64(lr);
             const double u2 = ux * ux + uy * uy + uz * uz;
             acc.mass += rho;
-            acc.ke += 0.5 * rho * u2;
+            acc.ke += 0.5 * (rho * u2);
             acc.slr += lr;
             const double um = sqrt(u2);
             acc.umax = um > acc.umax ? um : acc.umax;
@@ -186,8 +188,12 @@ __global__ __launch_bounds__(kRedThreads) void reduce_final_kernel(const double*
     __shared__ double out[kReduceSlots];
     block_reduce_store(acc, out);
     if (threadIdx.x == 0) {
-        result[0] = out[0] * dV;
-        result[1] = out[1] * dV;
+        // with a non-finite value anywhere, mass and kinetic energy are
+        // reported as NaN (the clamped exponential would otherwise turn a
+        // NaN lnrho into a large finite term)
+        const bool bad = out[4] > 0.0;
+        result[0] = bad ? __builtin_nan("") : out[0] * dV;
+        result[1] = bad ? __builtin_nan("") : out[1] * dV;
         result[2] = out[2];
         result[3] = out[3];
         result[4] = out[4];

@@ -46,6 +46,12 @@ struct fd6_box {
     int cur = 0;
     int tile = 6;  // z-sweep shape; fd6_create picks it by precision
     int zchunk = 0;  // z-sweep chunk length, 0: automatic
+    // candidates timed by the last fd6_tune call: (tile, zchunk, ms per step)
+    struct TuneTrial {
+        int tile, zchunk;
+        float ms;
+    };
+    std::vector<TuneTrial> tune_log;
     bool ghosts_ok[2] = {false, false};  // ghost zone of each state set is current
     std::string err;
     // optional per-launch event timing
@@ -134,6 +140,8 @@ struct fd6_batch {
 namespace {
 
 constexpr size_t kAlign = 256;
+// Shortest z chunk of a batch work item (each chunk re-reads 6 planes).
+constexpr int kMinBatchChunk = 8;
 constexpr long long kMaxFieldElems = (1LL << 31) - 1;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -669,8 +677,11 @@ int make_batch_plan(int n, const fd6_desc* d, BatchPlan* bp) {
         bp->base[i] = off;
         // this box's state and w fields (the per-box plan puts them first)
         off += bp->box[i].off_div;
-        // work items of the smallest tile (32 x 2) and z chunks of >= 8 planes
-        items += (long long)((d[i].nx + 31) / 32) * ((d[i].ny + 1) / 2) * ((d[i].nz + 7) / 8);
+        // work items of the smallest tile extents (x 32, y 4) with chunks of at
+        // least kMinBatchChunk planes (an even split into ceil(nz / zchunk)
+        // chunks never makes more than ceil(nz / kMinBatchChunk))
+        items += (long long)((d[i].nx + 31) / 32) * ((d[i].ny + 3) / 4) *
+                 ((d[i].nz + kMinBatchChunk - 1) / kMinBatchChunk);
         const long long pc = (long long)d[i].nx * d[i].ny;
         long long st = std::min<long long>(pc * d[i].nz, std::max<long long>(pc, 1LL << 22));
         stag = std::max(stag, st);
@@ -710,19 +721,23 @@ int upload_boxes(fd6_batch* b) {
     return FD6_OK;
 }
 
-// Work list for the current kernel shape: all tile-chunks, longest first
-// (then box, then z, y, x order so that neighbouring tiles stay adjacent).
+// Work list for kernel shape `tile` and chunk length `zchunk`: all
+// tile-chunks, longest first (then box, then z, y, x order so that
+// neighbouring tiles stay adjacent).  The batch's schedule, item list and
+// grid change only when the list is built and uploaded; a refused schedule
+// leaves the previous one in force.
 template <typename T, typename TW>
-int build_items(fd6_batch* b) {
+int build_items(fd6_batch* b, int tile, int zchunk) {
     int tx = 0, ty = 0;
-    if (substep55_tile_dims(b->tile, &tx, &ty)) return FD6_EINVAL;
+    if (substep55_tile_dims(tile, &tx, &ty)) return FD6_EINVAL;
+    if (zchunk > 0 && zchunk < kMinBatchChunk) return FD6_EINVAL;
     std::vector<BatchItem> it;
     std::vector<long long> cost;
     for (int i = 0; i < b->n; ++i) {
         const Geom& g = b->geom[i];
         // chunks of at most zchunk planes, split evenly (96 planes with 64-plane
         // chunks give 48 + 48, not 64 + 32)
-        const int cap = b->zchunk > 0 ? std::min(b->zchunk, g.nz) : g.nz;
+        const int cap = zchunk > 0 ? std::min(zchunk, g.nz) : g.nz;
         const int nch = (g.nz + cap - 1) / cap;
         const int zl = (g.nz + nch - 1) / nch;
         for (int zb = 0; zb < g.nz; zb += zl)
@@ -732,26 +747,33 @@ int build_items(fd6_batch* b) {
                     cost.push_back((long long)(std::min(zb + zl, g.nz) - zb + 2 * kR));
                 }
     }
-    if ((long long)it.size() > b->items_cap) return FD6_EUNSUPPORTED;
+    // the workspace holds the list of the smallest tile with chunks of
+    // kMinBatchChunk planes, so this cannot trigger for an accepted schedule
+    if ((long long)it.size() > b->items_cap) {
+        b->err = "work list larger than the workspace's item capacity";
+        return FD6_EUNSUPPORTED;
+    }
     std::vector<int> order(it.size());
     for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return cost[a] > cost[c]; });
     std::vector<BatchItem> sorted(it.size());
     for (size_t k = 0; k < order.size(); ++k) sorted[k] = it[order[k]];
-    b->nitems = (int)sorted.size();
-    HIPCHK(b, hipMemcpyAsync(b->items_dev, sorted.data(), sizeof(BatchItem) * sorted.size(),
-                             hipMemcpyHostToDevice, b->stream));
-    HIPCHK(b, hipStreamSynchronize(b->stream));
     // persistent grid: every resident workgroup, a multiple of the 8 XCDs
     int dev = 0, cus = 0;
     HIPCHK(b, hipGetDevice(&dev));
     HIPCHK(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per_cu = b->aos ? batch55_blocks_per_cu_aos<T, TW>(b->tile)
-                              : batch55_blocks_per_cu<T, TW>(b->tile);
+    const int per_cu = b->aos ? batch55_blocks_per_cu_aos<T, TW>(tile)
+                              : batch55_blocks_per_cu<T, TW>(tile);
+    HIPCHK(b, hipMemcpyAsync(b->items_dev, sorted.data(), sizeof(BatchItem) * sorted.size(),
+                             hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));
     long long gsz = (long long)cus * per_cu;
-    gsz = std::min<long long>(gsz, b->nitems);
+    gsz = std::min<long long>(gsz, (long long)sorted.size());
     if (gsz >= 8) gsz = gsz / 8 * 8;
+    b->tile = tile;
+    b->zchunk = zchunk;
+    b->nitems = (int)sorted.size();
     b->grid = (int)std::max<long long>(gsz, 1);
     b->drop_graphs();
     return FD6_OK;
@@ -791,7 +813,7 @@ int build_graphs(fd6_batch* b) {
 template <typename T, typename TW>
 int batch_steps(fd6_batch* b, int nsteps) {
     if (b->nitems == 0) {
-        int rc = build_items<T, TW>(b);
+        int rc = build_items<T, TW>(b, b->tile, b->zchunk);
         if (rc) return rc;
     }
     if (b->use_graph && !b->graph_ok) {
@@ -1267,6 +1289,7 @@ int fd6_tune(fd6_box* b, const char* cache_path) {
     return guarded(b, [&]() -> int {
         const std::string key = box_tune_key(b);
         int tile = 0, zchunk = 0;
+        b->tune_log.clear();
         if (cache_path && read_tune_cache(cache_path, key, &tile, &zchunk) &&
             fd6_set_tile(b, tile) == FD6_OK && fd6_set_zchunk(b, zchunk) == FD6_OK)
             return FD6_OK;
@@ -1289,6 +1312,8 @@ int fd6_tune(fd6_box* b, const char* cache_path) {
                 HIPCHK(b, hipEventRecord(ev.b, b->stream));
                 HIPCHK(b, hipEventSynchronize(ev.b));
                 HIPCHK(b, hipEventElapsedTime(ms, ev.a, ev.b));
+                *ms /= kBoxTuneSteps;
+                b->tune_log.push_back(fd6_box::TuneTrial{cand, zc, *ms});
                 return FD6_OK;
             };
             int rc = FD6_OK, best_tile = b->tile, best_zc = b->zchunk;
@@ -1316,6 +1341,19 @@ int fd6_tune(fd6_box* b, const char* cache_path) {
             return rc;
         });
     });
+}
+
+int fd6_get_tune_log(const fd6_box* b, int32_t* tiles, int32_t* zchunks, float* ms,
+                     int32_t cap, int32_t* n) {
+    if (!b || !n || cap < 0 || (cap > 0 && (!tiles || !zchunks || !ms))) return FD6_EINVAL;
+    const int32_t total = (int32_t)b->tune_log.size();
+    for (int32_t i = 0; i < total && i < cap; ++i) {
+        tiles[i] = b->tune_log[i].tile;
+        zchunks[i] = b->tune_log[i].zchunk;
+        ms[i] = b->tune_log[i].ms;
+    }
+    *n = total;
+    return FD6_OK;
 }
 
 int fd6_batch_workspace_bytes(int32_t n, const fd6_desc* descs, size_t* bytes) {
@@ -1419,15 +1457,15 @@ int fd6_batch_init_fields(fd6_batch* b, int32_t box, const double* lnrho, const 
 
 int fd6_batch_set_schedule(fd6_batch* b, int32_t tile, int32_t zchunk) {
     int tx, ty;
-    if (!b || zchunk < 0 || substep55_tile_dims(tile, &tx, &ty)) return FD6_EINVAL;
+    if (!b || zchunk < 0 || (zchunk > 0 && zchunk < kMinBatchChunk) ||
+        substep55_tile_dims(tile, &tx, &ty))
+        return FD6_EINVAL;
     if (b->aos && !substep55_aos_tile_ok(tile)) return FD6_EUNSUPPORTED;
     return guarded(b, [&]() -> int {
-        b->tile = tile;
-        b->zchunk = zchunk;
         return batch_dispatch(b, [&](auto* t, auto* tw) -> int {
             using T = std::remove_pointer_t<decltype(t)>;
             using TW = std::remove_pointer_t<decltype(tw)>;
-            return build_items<T, TW>(b);
+            return build_items<T, TW>(b, tile, zchunk);
         });
     });
 }
@@ -1476,16 +1514,15 @@ int fd6_batch_tune(fd6_batch* b, const char* cache_path) {
             EventPair ev;
             HIPCHK(b, ev.create());
             float best_ms = -1.0f;
-            int best_tile = b->tile, best_zc = b->zchunk;
+            const int old_tile = b->tile, old_zc = b->zchunk;
+            int best_tile = old_tile, best_zc = old_zc;
             int rc = FD6_OK;
             for (int cand = 1; cand < substep55_tile_count() && rc == FD6_OK; ++cand) {
                 int tx, ty;
                 if (substep55_tile_dims(cand, &tx, &ty) != 0) continue;
                 if (b->aos && !substep55_aos_tile_ok(cand)) continue;
                 for (int zc : kBatchTuneChunks) {
-                    b->tile = cand;
-                    b->zchunk = zc;
-                    if ((rc = build_items<T, TW>(b)) != FD6_OK) break;
+                    if ((rc = build_items<T, TW>(b, cand, zc)) != FD6_OK) break;
                     if ((rc = batch_steps<T, TW>(b, 1)) != FD6_OK) break;  // warm-up, capture
                     HIPCHK(b, hipEventRecord(ev.a, b->stream));
                     if ((rc = batch_steps<T, TW>(b, kBatchTuneSteps)) != FD6_OK) break;
@@ -1496,9 +1533,12 @@ int fd6_batch_tune(fd6_batch* b, const char* cache_path) {
                     if (best_ms < 0.0f || ms < best_ms) best_ms = ms, best_tile = cand, best_zc = zc;
                 }
             }
-            b->tile = best_tile;
-            b->zchunk = best_zc;
-            if (rc == FD6_OK) rc = build_items<T, TW>(b);
+            if (rc != FD6_OK) {
+                // a failed trial leaves the schedule that was in force before
+                (void)build_items<T, TW>(b, old_tile, old_zc);
+                return rc;
+            }
+            rc = build_items<T, TW>(b, best_tile, best_zc);
             if (rc == FD6_OK && cache_path) write_tune_cache(cache_path, key, best_tile, best_zc);
             return rc;
         });

@@ -127,7 +127,8 @@ struct Pass2Regs {
     T dx[4], dy[4];  // x / y first derivatives of d, ring of 4 planes
     T pf;        // prefetched interior value of the next plane
     T ph[NH];    // prefetched halo values of the next plane
-    double red[5];  // RED: FP64 diagnostics of the thread's column
+    double red[4];  // RED: FP64 diagnostics of the thread's column
+    int bad;        // RED: points of the column with a non-finite value
 };
 
 // As in the 55-point sweep, no memory operation of a step sits behind a
@@ -202,8 +203,9 @@ __device__ __forceinline__ void pass2_step(int t0, int nplanes, int zb, Pass2Reg
             un[i] = T(TW(ov[i]) + rk.beta * tq);
             bstore<CP>(un[i], plane_rsrc(out.f[1 + i] + ocorner, ob), X.lane_o);
         }
-        if constexpr (RED)
-            red_point(R.red, outstep && X.lane_o != kDropOffset, lr, un[0], un[1], un[2]);
+        if constexpr (RED) {
+            if (outstep && X.lane_o != kDropOffset) red_point(R.red, R.bad, lr, un[0], un[1], un[2]);
+        }
     }
 }
 
@@ -234,7 +236,8 @@ __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __res
 #pragma unroll
     for (int s = 0; s < 4; ++s) R.dx[s] = R.dy[s] = T(0);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) R.red[i] = 0.0;
+    for (int i = 0; i < 4; ++i) R.red[i] = 0.0;
+    R.bad = 0;
     const int zb = tl.zb;
     const int nplanes = (tl.ze - zb) + 2 * kR;
     pass2_prefetch<T, TX, TY, NH>(R, X, dv, plane_corner(g, zb - kR), X.plane_bytes);
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(TX* TY) void substep19_pass2(Geom g, const T* __res
         pass2_step<6, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
         pass2_step<7, S, NT, RED>(t0, nplanes, zb, R, X, lds, g, dv, out, w, cf, rk, cgd);
     }
-    if constexpr (RED) red_store_n<Sh::NW>(R.red, part);
+    if constexpr (RED) red_store_n<Sh::NW>(R.red, R.bad, part);
 }
 
 }  // namespace

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <type_traits>
 
+#include "exp_fp64.hpp"
 #include "fd6_internal.hpp"
 
 namespace fd6 {
@@ -304,27 +305,35 @@ __device__ __forceinline__ TileXY sweep_tile_of(const Geom& g, int TX, int TY,
     return TileXY{tix * TX, tiy * TY, zb, min(zb + m.zlen, g.nz)};
 }
 
-// FP64 diagnostics of the new state (the quantities of the standalone
-// reduction): per thread, red = {sum rho, sum rho |u|^2 / 2, sum lnrho,
-// max |u|^2, non-finite count}; invalid points (no output, outside the box)
-// add nothing.
-__device__ __forceinline__ void red_point(double red[5], bool valid, double lr, double ux,
-                                          double uy, double uz) {
-    const double rho = exp(lr);
-    const double u2 = ux * ux + uy * uy + uz * uz;
-    const bool finite = isfinite(lr) && isfinite(ux) && isfinite(uy) && isfinite(uz);
-    red[0] += valid ? rho : 0.0;
-    red[1] += valid ? 0.5 * rho * u2 : 0.0;
-    red[2] += valid ? lr : 0.0;
-    red[3] = (valid && u2 > red[3]) ? u2 : red[3];
-    red[4] += (valid && !finite) ? 1.0 : 0.0;
+// FP64 diagnostics of one point of the new state (the quantities of the
+// standalone reduction): per thread, red = {sum rho, sum rho |u|^2, sum
+// lnrho, max |u|^2} and bad = points holding a non-finite value.  The caller
+// skips points that are not outputs (branches, not selects, so the skipped
+// steps and lanes cost no FP64 instructions).  The kinetic energy's factor
+// 1/2 is applied once per workgroup (exact).  Non-finite values are found by
+// class checks of the stored values; the mass and kinetic-energy terms of
+// such a point are meaningless and the final combination reports them as
+// NaN whenever bad > 0.
+template <typename T>
+__device__ __forceinline__ void red_point(double red[4], int& bad, T lr, T ux, T uy, T uz) {
+    const bool finite = __builtin_isfinite(lr) && __builtin_isfinite(ux) &&
+                        __builtin_isfinite(uy) && __builtin_isfinite(uz);
+    bad += finite ? 0 : 1;
+    const double l = (double)lr, a = (double)ux, b = (double)uy, c = (double)uz;
+    const double rho = exp_fp64(l);
+    const double u2 = a * a + b * b + c * c;
+    red[0] += rho;
+    red[1] += rho * u2;
+    red[2] += l;
+    red[3] = __builtin_fmax(red[3], u2);
 }
 
 // Combines the per-thread diagnostics of a workgroup in a fixed order (xor
 // tree within each wave, then waves in order) and stores the partial:
 // sums for slots 0-2 and 4, the maximum for slot 3.
 template <int NW>
-__device__ __forceinline__ void red_store_n(double v[5], double* part) {
+__device__ __forceinline__ void red_store_n(const double red[4], int bad, double* part) {
+    double v[5] = {red[0], 0.5 * red[1], red[2], red[3], (double)bad};
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll

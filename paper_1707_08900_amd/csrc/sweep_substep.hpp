@@ -167,8 +167,9 @@ struct SweepRegs {
     T pf[4][4];      // prefetched interior values of the next plane(s)
     T ph[4][NH][4];  // prefetched halo values of the next plane(s)
     TW wq[2][4];     // RK3 register of the output point (PD = 2: loaded a step early)
-    double red[5];   // fused diagnostics of the thread's column (RED): sum rho,
-                     // sum rho u^2 / 2, sum lnrho, max u^2, non-finite count
+    double red[4];   // fused diagnostics of the thread's column (RED): sum rho,
+                     // sum rho u^2, sum lnrho, max u^2
+    int bad;         // RED: points of the column with a non-finite value
     T fc, fs;        // FRC: cos / sin(kx x + ky y) of the thread's column
     T fa[3];         // FRC: force amplitude vector
 };
@@ -410,9 +411,10 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             bstore(J[0][0] + J[1][1] + J[2][2], plane_rsrc(dv + ocorner, ob), X.lane_o);
         // FP64 diagnostics of the new state, from the values just stored (the
         // same per-point quantities as the standalone reduction)
-        if constexpr (RED)
-            red_point(R.red, outstep && X.lane_o != kDropOffset, vout[0], vout[1], vout[2],
-                      vout[3]);
+        if constexpr (RED) {
+            if (outstep && X.lane_o != kDropOffset)
+                red_point(R.red, R.bad, vout[0], vout[1], vout[2], vout[3]);
+        }
     }
 
     // (C) the rest of plane p for this column: x / y first derivatives of the
@@ -566,7 +568,8 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
 #pragma unroll
         for (int s = 0; s < 8; ++s) R.L[i][s] = T(0);
 #pragma unroll
-    for (int i = 0; i < 5; ++i) R.red[i] = 0.0;
+    for (int i = 0; i < 4; ++i) R.red[i] = 0.0;
+    R.bad = 0;
     if constexpr (FRC) {
         const ForceDev<T>* fd = fa.dev;
         const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -610,7 +613,7 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         sweep_step<7, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
                                                       out, w, dv, cf, rk, fa.tab);
     }
-    if constexpr (RED) red_store_n<SweepShape<T, TX, TY, LD>::NW>(R.red, part);
+    if constexpr (RED) red_store_n<SweepShape<T, TX, TY, LD>::NW>(R.red, R.bad, part);
 }
 
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS,

@@ -200,3 +200,39 @@ def test_box_tuner_argument_checks(pkg):
     t, z = ctypes.c_int32(), ctypes.c_int32()
     assert lib.fd6_tune(None, None) == -1
     assert lib.fd6_get_schedule(None, ctypes.byref(t), ctypes.byref(z)) == -1
+    # the tuning log: argument checks, and empty before any tuning
+    d = desc(nx=8, ny=8, nz=8, prec=1)
+    need = ctypes.c_size_t()
+    lib.fd6_workspace_bytes(ctypes.byref(d), ctypes.byref(need))
+    h = ctypes.c_void_p()
+    assert lib.fd6_create(ctypes.byref(d), ctypes.c_void_p(1 << 40), need.value, None,
+                          ctypes.byref(h)) == 0
+    try:
+        n = ctypes.c_int32(-1)
+        assert lib.fd6_get_tune_log(h, None, None, None, 0, ctypes.byref(n)) == 0 and n.value == 0
+        assert lib.fd6_get_tune_log(h, None, None, None, 0, None) == -1
+        assert lib.fd6_get_tune_log(h, None, None, None, -1, ctypes.byref(n)) == -1
+        assert lib.fd6_get_tune_log(h, None, None, None, 4, ctypes.byref(n)) == -1
+        assert lib.fd6_get_tune_log(None, None, None, None, 0, ctypes.byref(n)) == -1
+    finally:
+        lib.fd6_destroy(h)
+
+
+def test_batch_schedule_rejects_short_chunks_before_any_device_call(pkg):
+    """Chunks of 1-7 planes are refused up front (FD6_EINVAL), so the check
+    needs no device."""
+    lib = pkg.library()
+    arr = (pkg.Fd6Desc * 2)(desc(8, 8, 8), desc(16, 12, 10))
+    out = ctypes.c_size_t()
+    assert lib.fd6_batch_workspace_bytes(2, arr, ctypes.byref(out)) == 0
+    h = ctypes.c_void_p()
+    assert lib.fd6_batch_create(2, arr, ctypes.c_void_p(1 << 40), out.value, None,
+                                ctypes.byref(h)) == 0
+    try:
+        for zc in range(1, 8):
+            assert lib.fd6_batch_set_schedule(h, 6, zc) == -1, zc
+        t, z = ctypes.c_int32(), ctypes.c_int32()
+        assert lib.fd6_batch_get_schedule(h, ctypes.byref(t), ctypes.byref(z)) == 0
+        assert (t.value, z.value) == (8, 64)  # the default stays in force
+    finally:
+        lib.fd6_batch_destroy(h)

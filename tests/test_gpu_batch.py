@@ -90,10 +90,8 @@ def test_uneven_ensemble_sample(fd6, orc):
     ws = [m.workload for m in members]
     out, _ = run_batch(fd6, ws, "fp32", 1)
     for i, w in enumerate(ws):
-        if w.shape[0] > 48:
-            continue  # the oracle check covers the smaller boxes
         inp = si.as_float32_exact(w.fields)
-        ref = orc.rk3(inp, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1)
+        ref = orc.rk3(inp, w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 1, 16)
         err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(out[i], ref))
         assert err <= 1e-5, (i, err)
 
@@ -121,6 +119,29 @@ def test_tuner_picks_a_valid_schedule_and_caches_it(fd6, tmp_path):
     b.step(2)
     for i, w in enumerate(ws):
         ref, _ = run_single(fd6, w, "fp32", 2, tile)
+        for x, y in zip(b.get_fields(i), ref):
+            assert np.array_equal(x, y), (i, w.shape)
+    b.close()
+
+
+def test_refused_schedule_leaves_the_schedule_in_force(fd6):
+    """fd6_batch_set_schedule refuses chunks of 1-7 planes and bad shapes;
+    the schedule in force, its work list and the results stay those of the
+    last accepted call."""
+    ws = small_ensemble()
+    b = fd6.Batch([w.shape for w in ws], "fp32", layout="aos")
+    b.set_params([(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt) for w in ws])
+    for i, w in enumerate(ws):
+        b.init_fields(i, w.fields)
+    b.set_schedule(6, 16)
+    for tile, zc, status in ((1, 1, -1), (6, 7, -1), (0, 16, -1), (9, 16, -6), (99, 16, -1)):
+        with pytest.raises(fd6.Fd6Error) as ex:
+            b.set_schedule(tile, zc)
+        assert ex.value.status == status, (tile, zc)
+        assert b.get_schedule() == (6, 16)
+    b.step(2)
+    for i, w in enumerate(ws):
+        ref, _ = run_single(fd6, w, "fp32", 2, 6)
         for x, y in zip(b.get_fields(i), ref):
             assert np.array_equal(x, y), (i, w.shape)
     b.close()

@@ -218,9 +218,20 @@ def test_library_tuner_single_box(fd6, layout, tmp_path):
     tile, zc = box.tune(cache)
     assert 1 <= tile < fd6.tile_count() and (layout == "soa" or tile != 9)
     assert zc in (0, 40) or zc in (64, 128, 256)
+    # the log: every shape the layout takes with the automatic chunk, then
+    # the chunk lengths (here only nz = 40) for the fastest shape
+    log = box.tune_log()
+    shapes = [t for t, z, _ in log if z == 0]
+    assert shapes == [t for t in range(1, fd6.tile_count()) if layout == "soa" or t != 9]
+    assert all(ms > 0 for _, _, ms in log)
+    fastest = min((ms, t) for t, z, ms in log if z == 0)[1]
+    assert [(t, z) for t, z, _ in log if z != 0] == [(fastest, 40)]
+    best = min(log, key=lambda e: e[2])
+    assert (tile, zc) == (best[0], best[1])
     box.set_tile(default[0])
     box.set_zchunk(default[1])
     assert box.tune(cache) == (tile, zc)  # from the cache
+    assert box.tune_log() == []
     assert len([ln for ln in open(cache).read().split("\n") if ln]) == 1
     box.init_fields(w.fields)
     box.step(2)

@@ -4,7 +4,8 @@ same seeded inputs.
 Tolerances (per field, ||gpu - oracle||_inf / ||oracle||_inf):
   FP64            1e-12 after one full step (3 substeps)
   FP32            1e-5 after one step
-  FP32 + FP64 w   no worse than FP32
+  FP32 + FP64 w   1e-5, and after one step no worse than FP32 (max norm
+                  within 5%, RMS)
 FP32 inputs are the FP64 generator values rounded to float32 on the host by
 numpy; the oracle receives the same rounded values.
 """
@@ -62,6 +63,28 @@ def test_small_box_one_step_all_kernels(fd6, orc, precision):
         errs[tile] = rel_err(out, ref)
         print(f"32^3 {precision} tile {tile}: rel err {errs[tile]:.3e}", flush=True)
     assert max(errs.values()) <= TOL[precision], errs
+
+
+@pytest.mark.parametrize("box", ["noise32", "fourier64"])
+def test_acc64_no_worse_than_fp32_one_step(fd6, orc, box):
+    """FP32 state with the FP64 RK3 register and FP64 RK3 arithmetic against
+    plain FP32, both against the oracle on the same FP32-rounded inputs,
+    after one step: no worse in the max norm (5% allowed for the scatter of
+    two rounding-noise maxima) and in the RMS."""
+    w = (si.small_parity_box(seed=2) if box == "noise32" else
+         si.fourier_box(64, seed=1, amplitude=0.1, kmax=16.0, nu=1e-3))
+    ref = run_oracle(orc, w, "fp32")
+    o32, oacc = run_gpu(fd6, w, "fp32"), run_gpu(fd6, w, "fp32_acc64")
+
+    def rms(a, b):
+        return max(float(np.sqrt(np.mean((x - y) ** 2)) / np.max(np.abs(y)))
+                   for x, y in zip(a, b))
+    e32, eacc = rel_err(o32, ref), rel_err(oacc, ref)
+    r32, racc = rms(o32, ref), rms(oacc, ref)
+    print(f"{box} one step: fp32 {e32:.4e} (rms {r32:.4e}), fp32 + fp64 w {eacc:.4e} "
+          f"(rms {racc:.4e})", flush=True)
+    assert e32 <= TOL["fp32"]
+    assert eacc <= 1.05 * e32 and racc <= r32
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -133,10 +156,13 @@ def test_mid_box_several_steps_fp64(fd6, orc):
         assert rel_err(out, ref) <= 1e-11
 
 
-def test_sweep_tiles_are_bitwise_identical(fd6):
+@pytest.mark.parametrize("precision,shape", [("fp32", (20, 21, 70)), ("fp32", (32, 32, 32)),
+                                             ("fp64", (32, 32, 32)),
+                                             ("fp32_acc64", (32, 32, 32))])
+def test_sweep_tiles_are_bitwise_identical(fd6, precision, shape):
     """Every z-sweep tile shape performs the same arithmetic per point."""
-    w = si.noise_box((20, 21, 70), seed=8)
-    outs = [run_gpu(fd6, w, "fp32", nsteps=2, tile=t) for t in range(1, fd6.tile_count())]
+    w = si.noise_box(shape, seed=8)
+    outs = [run_gpu(fd6, w, precision, nsteps=2, tile=t) for t in range(1, fd6.tile_count())]
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
@@ -265,7 +291,37 @@ def test_reduce_reports_nonfinite(fd6):
     with pytest.raises(fd6.Fd6Error) as e:
         box.reduce()
     assert e.value.status == -5
-    assert box.reduce(allow_nonfinite=True)["nonfinite"] == 2
+    r = box.reduce(allow_nonfinite=True)
+    assert r["nonfinite"] == 2 and np.isnan(r["mass"]) and np.isnan(r["kinetic_energy"])
+
+
+@pytest.mark.parametrize("variant,precision", [("55p", "fp32"), ("55p", "fp64"),
+                                               ("19p", "fp32")])
+def test_fused_diagnostics_count_nonfinite(fd6, variant, precision):
+    """A NaN and an infinity planted in the state spread over their stencil
+    neighbourhoods in one step; the diagnostics fused into the last substep
+    count the same non-finite points as the standalone pass, and both report
+    mass and kinetic energy as NaN."""
+    import torch
+    w = si.noise_box((20, 18, 40), seed=21)
+    f = [a.copy() for a in w.fields]
+    f[2][5, 6, 7] = np.nan
+    f[0][12, 3, 30] = np.inf
+    box = fd6.Box(w.shape, precision, variant)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(f)
+    red = torch.zeros(8, dtype=torch.float64, device="cuda")
+    box.step_reduce(1, red)
+    fused = red.cpu().numpy()
+    alone = box.reduce(allow_nonfinite=True)
+    out = box.get_fields()
+    box.close()
+    bad = int(np.sum(~(np.isfinite(out[0]) & np.isfinite(out[1]) & np.isfinite(out[2]) &
+                       np.isfinite(out[3]))))
+    print(f"{variant} {precision}: {bad} non-finite points after one step", flush=True)
+    assert bad > 2 and fused[4] == bad and alone["nonfinite"] == bad
+    assert np.isnan(fused[0]) and np.isnan(fused[1])
+    assert np.isnan(alone["mass"]) and np.isnan(alone["kinetic_energy"])
 
 
 def test_checkpoint_restart_bitwise(fd6):
