@@ -263,6 +263,31 @@ int fd6_get_timing(fd6_box *box, double *kernel_ms, int64_t *kernel_launches, do
 /* Text of the last error on this handle ("" if none). */
 const char *fd6_last_error(const fd6_box *box);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * diagnostics of fd6_reduce_device computed from four caller-owned compact
+ * device arrays (nx*ny*nz values each, [z][y][x], x fastest), without a box
+ * and without any allocation.  precision: FD6_FP64 for double arrays,
+ * FD6_FP32 or FD6_FP32_ACC64 for float arrays.  dx, dy, dz > 0 give the cell
+ * volume of the mass and kinetic-energy sums.  d_out5: device buffer of 5
+ * doubles (mass, kinetic energy, sum lnrho, max |u|, non-finite count),
+ * written asynchronously on `stream` (a hipStream_t or NULL).  The same
+ * kernels and the same fixed summation order as fd6_reduce_device, so a box
+ * holding the same values gives the same result.
+ * Scratch: the partial sums live in a static device array of the library
+ * (1024 x 8 doubles = 64 KiB per device, kept until the process ends; its
+ * address is looked up once per device, on the first call with that device
+ * current).  Every call on a device shares that array: calls that overlap on
+ * one device (different streams or threads) race and must be serialised by
+ * the caller.  Nothing needs clearing between calls.
+ * FD6_EINVAL for null pointers, an unknown precision, non-positive or
+ * non-finite spacings, or a grid dimension outside 1..4096 (the largest grid
+ * the fixed partial count is sized for); FD6_EHIP if a HIP call fails. */
+int fd6_reduce_fields_static(int32_t nx, int32_t ny, int32_t nz, int32_t precision,
+                             const void *lnrho, const void *ux, const void *uy,
+                             const void *uz, double dx, double dy, double dz, void *stream,
+                             double *d_out5);
+
 /* ---------------------------------------------------------------------------
  * Batched ensemble: n independent periodic boxes of possibly different sizes
  * and parameters, all with the same precision and the 55-point method,

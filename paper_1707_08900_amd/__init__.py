@@ -45,7 +45,7 @@ ABI_SYMBOLS = (
     "fd6_batch_set_params", "fd6_batch_init_fields", "fd6_batch_set_schedule",
     "fd6_batch_tune", "fd6_batch_get_schedule",
     "fd6_batch_set_graph", "fd6_batch_step", "fd6_batch_get_fields", "fd6_batch_reduce",
-    "fd6_batch_last_error",
+    "fd6_batch_last_error", "fd6_reduce_fields_static",
 )
 
 
@@ -129,6 +129,9 @@ def _declare(lib):
         "fd6_batch_get_fields": (I, [P, ctypes.c_int32, D, D, D, D]),
         "fd6_batch_reduce": (I, [P, ctypes.POINTER(Fd6Reductions)]),
         "fd6_batch_last_error": (ctypes.c_char_p, [P]),
+        "fd6_reduce_fields_static": (I, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, P, P, P, P, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -441,3 +444,24 @@ class Batch:
 def tile_count() -> int:
     return library().fd6_tile_count()
 
+
+def reduce_fields_static(fields, dx: float, dy: float, dz: float, out: torch.Tensor,
+                         stream: Optional[torch.cuda.Stream] = None) -> None:
+    """FP64 diagnostics of four compact device tensors (float32 or float64,
+    shape (nz, ny, nx)) into the 5-element float64 device tensor `out`,
+    asynchronously, through the library entry point that allocates nothing
+    (its partial sums live in a static device array shared by every call on
+    the device)."""
+    ts = list(fields)
+    assert len(ts) == 4 and all(t.is_cuda and t.is_contiguous() for t in ts)
+    dt = ts[0].dtype
+    assert ts[0].dim() == 3 and all(t.dtype == dt and t.shape == ts[0].shape for t in ts)
+    prec = {torch.float64: PRECISIONS["fp64"], torch.float32: PRECISIONS["fp32"]}[dt]
+    assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= 5
+    nz, ny, nx = (int(v) for v in ts[0].shape)
+    st = stream if stream is not None else torch.cuda.current_stream(ts[0].device)
+    rc = library().fd6_reduce_fields_static(
+        nx, ny, nz, prec, *[ctypes.c_void_p(t.data_ptr()) for t in ts], float(dx), float(dy),
+        float(dz), ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(out.data_ptr()))
+    if rc != 0:
+        raise Fd6Error(rc, "fd6_reduce_fields_static")

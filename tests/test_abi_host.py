@@ -236,3 +236,25 @@ def test_batch_schedule_rejects_short_chunks_before_any_device_call(pkg):
         assert (t.value, z.value) == (8, 64)  # the default stays in force
     finally:
         lib.fd6_batch_destroy(h)
+
+
+def test_reduce_fields_static_validation(pkg):
+    """The no-allocation diagnostics entry point rejects bad arguments before
+    touching the device."""
+    lib = pkg.library()
+    P = ctypes.c_void_p
+    f = [P(256 * (i + 1)) for i in range(4)]  # never dereferenced on these paths
+    out = P(4096)
+    ok = (8, 8, 8, 1, *f, 0.1, 0.1, 0.1, None, out)
+    names = ["nx", "ny", "nz", "prec", "f0", "f1", "f2", "f3", "dx", "dy", "dz", "st", "out"]
+
+    def call(**over):
+        a = list(ok)
+        for k, v in over.items():
+            a[names.index(k)] = v
+        return lib.fd6_reduce_fields_static(*a)
+
+    for bad in ({"nx": 0}, {"ny": -1}, {"nz": 4097}, {"prec": 3}, {"prec": -1},
+                {"f0": None}, {"f3": None}, {"out": None}, {"dx": 0.0}, {"dy": -1.0},
+                {"dz": float("nan")}, {"dx": float("inf")}):
+        assert call(**bad) == -1, bad
