@@ -319,21 +319,28 @@ int fd6_batch_set_params(fd6_batch *batch, const fd6_params *per_box);
 int fd6_batch_init_fields(fd6_batch *batch, int32_t box, const double *lnrho, const double *ux,
                           const double *uy, const double *uz);
 
-/* Kernel shape (1 .. fd6_tile_count()-1, a z-sweep shape) and z-chunk length
- * of the work items: each box's z range is split evenly into chunks of at
- * most zchunk planes (0 = whole boxes; otherwise zchunk >= 8, since every
- * chunk re-reads 6 planes).  Rebuilds the work list and drops any captured
- * graph.  FD6_EINVAL for a shape out of range or 0 < zchunk < 8;
+/* Kernel shape (1 .. fd6_tile_count()-1, a z-sweep shape) and work
+ * distribution of the persistent launch.  zchunk >= 0: each box's z range is
+ * split evenly into chunks of at most zchunk planes (0 = whole boxes;
+ * otherwise zchunk >= 8, since every chunk re-reads 6 planes), the chunks
+ * sorted longest first and dealt to the workgroups in turn.
+ * zchunk = FD6_BATCH_BALANCED: the tile columns of all boxes cut into one run
+ * of equal cost per workgroup (a column is split only where a run ends).
+ * Rebuilds the work lists and drops any captured graph.  FD6_EINVAL for a
+ * shape out of range, zchunk < 0 other than FD6_BATCH_BALANCED, or
+ * 0 < zchunk < 8;
  * FD6_EUNSUPPORTED for a shape the ensemble's layout does not take.  A
  * refused call leaves the schedule in force (and fd6_batch_get_schedule's
  * answer) unchanged.  Default: shape 8 (32 x 8, two planes ahead), chunks of
  * at most 64 planes. */
+#define FD6_BATCH_BALANCED (-1)
 int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
 
 /* Autotuner of the ensemble schedule (the shape and chunk choice is the
  * caller's tuning concern, not the method's): times every z-sweep shape the
  * ensemble's layout takes with z-chunk lengths 0 (whole boxes), 32, 48 and 64
- * -- one warm-up step, then 3 timed steps each, HIP events on the ensemble's
+ * and with FD6_BATCH_BALANCED -- one warm-up step, then 3 timed steps each,
+ * HIP events on the ensemble's
  * stream -- and keeps the fastest.  Advances every box by 4 steps per
  * candidate: call it before the fields of the actual run are set, or set
  * them again afterwards.  cache_path (may be NULL) names a text file of

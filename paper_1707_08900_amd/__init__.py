@@ -24,7 +24,8 @@ import numpy as np
 import torch  # loaded first: its HIP runtime is the one the library binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfd6.so")
+# FD6_LIB selects another build of the library (e.g. a host-sanitizer build)
+LIB_PATH = os.environ.get("FD6_LIB") or os.path.join(_HERE, "libfd6.so")
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_acc64": 2}
 VARIANTS = {"55p": 0, "19p": 1}

@@ -1,6 +1,9 @@
 """Build libfd6.so (HIP, gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1707_08900_amd.build [--verbose] [--resource-usage]
+Usage: python -m paper_1707_08900_amd.build [--verbose] [--resource-usage] [--incremental]
+       python -m paper_1707_08900_amd.build --host-sanitize --out DIR
+         (host code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer,
+          device code unchanged; the library and its objects go to DIR)
 """
 from __future__ import annotations
 
@@ -42,6 +45,11 @@ UNIT_FLAGS = {
 }
 
 
+# Host-side sanitizers only: each flag applies to the host compilation.
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
 def _up_to_date(src: str, obj: str) -> bool:
     """The object is newer than its source, every header of the library and
     this file (which holds the compiler options)."""
@@ -56,11 +64,12 @@ def _up_to_date(src: str, obj: str) -> bool:
     return all(os.path.getmtime(d) < t for d in deps)
 
 
-def _compile(src: str, resource_usage: bool, incremental: bool = False) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(src: str, resource_usage: bool, incremental: bool = False, build_dir: str = BUILD,
+             extra=()) -> str:
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
     if incremental and not resource_usage and _up_to_date(src, obj):
         return obj
-    cmd = [HIPCC, *COMMON, *UNIT_FLAGS.get(src, []), "-x", "hip", "-c",
+    cmd = [HIPCC, *COMMON, *UNIT_FLAGS.get(src, []), *extra, "-x", "hip", "-c",
            os.path.join(CSRC, src), "-o", obj]
     if resource_usage:
         cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
@@ -72,22 +81,28 @@ def _compile(src: str, resource_usage: bool, incremental: bool = False) -> str:
     return obj
 
 
-def build(verbose: bool = False, resource_usage: bool = False, incremental: bool = False) -> str:
+def build(verbose: bool = False, resource_usage: bool = False, incremental: bool = False,
+          host_sanitize: bool = False, out_dir: str = None) -> str:
     """Compile every unit (incremental: only units older than their source, a
-    header or this file) and link libfd6.so."""
-    os.makedirs(BUILD, exist_ok=True)
+    header or this file) and link libfd6.so (in out_dir if given, else in the
+    package)."""
+    build_dir = os.path.join(out_dir, "_build") if out_dir else BUILD
+    lib = os.path.join(out_dir, "libfd6.so") if out_dir else LIB
+    extra = HOST_SANITIZE if host_sanitize else []
+    os.makedirs(build_dir, exist_ok=True)
     jobs = min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, resource_usage, incremental), SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+        objs = list(ex.map(lambda s: _compile(s, resource_usage, incremental, build_dir, extra),
+                           SOURCES))
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
@@ -96,5 +111,9 @@ if __name__ == "__main__":
     ap.add_argument("--resource-usage", action="store_true")
     ap.add_argument("--incremental", action="store_true",
                     help="skip units whose object is newer than every source and header")
+    ap.add_argument("--host-sanitize", action="store_true",
+                    help="instrument the host code with AddressSanitizer and UBSan")
+    ap.add_argument("--out", default=None, help="directory for the library and its objects")
     a = ap.parse_args()
-    build(verbose=True, resource_usage=a.resource_usage, incremental=a.incremental)
+    build(verbose=True, resource_usage=a.resource_usage, incremental=a.incremental,
+          host_sanitize=a.host_sanitize, out_dir=a.out)

@@ -111,7 +111,8 @@ struct fd6_batch {
     int parity = 0;              // state set holding the current state (all boxes)
     void* boxes_dev = nullptr;   // BatchBox<T, TW>[n]
     size_t box_bytes = 0;
-    BatchItem* items_dev = nullptr;
+    BatchItem* items_dev = nullptr;  // every workgroup's items, workgroup by workgroup
+    int* wg_first_dev = nullptr;     // [grid + 1] offsets of the workgroups' lists
     long long items_cap = 0;
     int nitems = 0, grid = 0;
     double* partials = nullptr;
@@ -142,6 +143,8 @@ namespace {
 constexpr size_t kAlign = 256;
 // Shortest z chunk of a batch work item (each chunk re-reads 6 planes).
 constexpr int kMinBatchChunk = 8;
+// Schedule value of the z-chunk that selects the balanced partition.
+constexpr int kBatchBalanced = -1;
 constexpr long long kMaxFieldElems = (1LL << 31) - 1;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -649,7 +652,7 @@ bool ready(fd6_box* b) { return b->have_params && b->have_fields; }
 struct BatchPlan {
     std::vector<Plan> box;
     std::vector<size_t> base;  // workspace offset of each box's fields
-    size_t off_boxes, off_items, off_partials, off_results, off_staging, total;
+    size_t off_boxes, off_items, off_wg, off_partials, off_results, off_staging, total;
     size_t box_bytes;
     long long items_cap, staging_elems;
 };
@@ -689,9 +692,13 @@ int make_batch_plan(int n, const fd6_desc* d, BatchPlan* bp) {
     bp->box_bytes = batch_box_bytes(d[0].precision);
     bp->off_boxes = off;
     off += round_up(bp->box_bytes * n, kAlign);
+    // a balanced partition adds at most one split per workgroup
+    items += kMaxBatchGrid;
     bp->items_cap = items;
     bp->off_items = off;
     off += round_up(sizeof(BatchItem) * items, kAlign);
+    bp->off_wg = off;
+    off += round_up(sizeof(int) * (kMaxBatchGrid + 1), kAlign);
     bp->off_partials = off;
     off += round_up((size_t)kReduceBlocks * kReduceSlots * sizeof(double), kAlign);
     bp->off_results = off;
@@ -721,60 +728,151 @@ int upload_boxes(fd6_batch* b) {
     return FD6_OK;
 }
 
-// Work list for kernel shape `tile` and chunk length `zchunk`: all
-// tile-chunks, longest first (then box, then z, y, x order so that
-// neighbouring tiles stay adjacent).  The batch's schedule, item list and
-// grid change only when the list is built and uploaded; a refused schedule
-// leaves the previous one in force.
+// Work lists for kernel shape `tile` and chunk length `zchunk`, one list per
+// workgroup of the persistent grid (workgroup L = remapped block index, so a
+// range of L lies on one XCD).
+//  * zchunk >= 0: every box's z range split evenly into chunks of at most
+//    zchunk planes (0: whole columns); all tile-chunks sorted longest first
+//    (then box, z, y, x), and workgroup L takes entries L, L + G, L + 2G, ...
+//    The first G entries are neighbouring tiles, swept at the same time.
+//  * zchunk = kBatchBalanced: the tile columns of all boxes in order (box, y,
+//    x), cut into G runs of equal cost (planes swept, 6 more per column piece
+//    for the pipeline refill); workgroup L sweeps run L, so every workgroup
+//    has the same work, and a column is split only where a run ends (pieces
+//    of at least kMinBatchChunk planes).
+// The batch's schedule, lists and grid change only when the lists are built
+// and uploaded; a refused schedule leaves the previous one in force.
 template <typename T, typename TW>
 int build_items(fd6_batch* b, int tile, int zchunk) {
     int tx = 0, ty = 0;
     if (substep55_tile_dims(tile, &tx, &ty)) return FD6_EINVAL;
-    if (zchunk > 0 && zchunk < kMinBatchChunk) return FD6_EINVAL;
-    std::vector<BatchItem> it;
-    std::vector<long long> cost;
-    for (int i = 0; i < b->n; ++i) {
-        const Geom& g = b->geom[i];
-        // chunks of at most zchunk planes, split evenly (96 planes with 64-plane
-        // chunks give 48 + 48, not 64 + 32)
-        const int cap = zchunk > 0 ? std::min(zchunk, g.nz) : g.nz;
-        const int nch = (g.nz + cap - 1) / cap;
-        const int zl = (g.nz + nch - 1) / nch;
-        for (int zb = 0; zb < g.nz; zb += zl)
-            for (int y0 = 0; y0 < g.ny; y0 += ty)
-                for (int x0 = 0; x0 < g.nx; x0 += tx) {
-                    it.push_back(BatchItem{i, x0, y0, zb, std::min(zb + zl, g.nz)});
-                    cost.push_back((long long)(std::min(zb + zl, g.nz) - zb + 2 * kR));
-                }
-    }
-    // the workspace holds the list of the smallest tile with chunks of
-    // kMinBatchChunk planes, so this cannot trigger for an accepted schedule
-    if ((long long)it.size() > b->items_cap) {
-        b->err = "work list larger than the workspace's item capacity";
-        return FD6_EUNSUPPORTED;
-    }
-    std::vector<int> order(it.size());
-    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int c) { return cost[a] > cost[c]; });
-    std::vector<BatchItem> sorted(it.size());
-    for (size_t k = 0; k < order.size(); ++k) sorted[k] = it[order[k]];
+    if (zchunk != kBatchBalanced && (zchunk < 0 || (zchunk > 0 && zchunk < kMinBatchChunk)))
+        return FD6_EINVAL;
     // persistent grid: every resident workgroup, a multiple of the 8 XCDs
     int dev = 0, cus = 0;
     HIPCHK(b, hipGetDevice(&dev));
     HIPCHK(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int per_cu = b->aos ? batch55_blocks_per_cu_aos<T, TW>(tile)
                               : batch55_blocks_per_cu<T, TW>(tile);
-    HIPCHK(b, hipMemcpyAsync(b->items_dev, sorted.data(), sizeof(BatchItem) * sorted.size(),
+    long long resident = std::min<long long>((long long)cus * per_cu, kMaxBatchGrid);
+    const long long pieces = 8;  // keep G a multiple of the XCD count
+    std::vector<BatchItem> flat;
+    std::vector<int> first;
+    if (zchunk != kBatchBalanced) {
+        std::vector<BatchItem> it;
+        std::vector<long long> cost;
+        for (int i = 0; i < b->n; ++i) {
+            const Geom& g = b->geom[i];
+            // chunks of at most zchunk planes, split evenly (96 planes with
+            // 64-plane chunks give 48 + 48, not 64 + 32)
+            const int cap = zchunk > 0 ? std::min(zchunk, g.nz) : g.nz;
+            const int nch = (g.nz + cap - 1) / cap;
+            const int zl = (g.nz + nch - 1) / nch;
+            for (int zb = 0; zb < g.nz; zb += zl)
+                for (int y0 = 0; y0 < g.ny; y0 += ty)
+                    for (int x0 = 0; x0 < g.nx; x0 += tx) {
+                        it.push_back(BatchItem{i, x0, y0, zb, std::min(zb + zl, g.nz)});
+                        cost.push_back((long long)(std::min(zb + zl, g.nz) - zb + 2 * kR));
+                    }
+        }
+        // the workspace holds the lists of the smallest tile with chunks of
+        // kMinBatchChunk planes, so this cannot trigger for an accepted schedule
+        if ((long long)it.size() > b->items_cap) {
+            b->err = "work list larger than the workspace's item capacity";
+            return FD6_EUNSUPPORTED;
+        }
+        std::vector<int> order(it.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int c) { return cost[a] > cost[c]; });
+        long long gsz = std::min<long long>(resident, (long long)it.size());
+        if (gsz >= pieces) gsz = gsz / pieces * pieces;
+        const int G = (int)std::max<long long>(gsz, 1);
+        flat.reserve(it.size());
+        first.assign(G + 1, 0);
+        for (int L = 0; L < G; ++L) {
+            first[L] = (int)flat.size();
+            for (size_t k = L; k < order.size(); k += G) flat.push_back(it[order[k]]);
+        }
+        first[G] = (int)flat.size();
+    } else {
+        struct Col {
+            int box, x0, y0, nz;
+        };
+        std::vector<Col> cols;
+        long long total = 0;
+        for (int i = 0; i < b->n; ++i) {
+            const Geom& g = b->geom[i];
+            for (int y0 = 0; y0 < g.ny; y0 += ty)
+                for (int x0 = 0; x0 < g.nx; x0 += tx) {
+                    cols.push_back(Col{i, x0, y0, g.nz});
+                    total += g.nz + 2 * kR;
+                }
+        }
+        long long gsz = resident >= pieces ? resident / pieces * pieces : resident;
+        const int G = (int)std::max<long long>(gsz, 1);
+        first.assign(G + 1, 0);
+        // Each run aims at the mean of the cost still unassigned over the
+        // runs still open (counting one refill per column not yet started and
+        // one per split still to come), so no shortfall piles up at the end.
+        long long left = total;  // planes + one refill per column, unassigned
+        int L = 0;
+        long long load = 0;
+        auto mean_left = [&]() { return (double)(left + (long long)(G - L - 1) * 2 * kR) / (G - L); };
+        double target = mean_left();
+        for (const Col& c : cols) {
+            int z = 0;
+            bool first_piece = true;
+            while (z < c.nz) {
+                const int rem = c.nz - z;
+                const double room = target - (double)load - 2 * kR;  // planes that fit
+                int take = rem;
+                if (L < G - 1 && rem > room) {
+                    take = (int)std::lround(room);
+                    if (take < kMinBatchChunk) {
+                        if (load > 0) {  // close this run; the piece opens the next
+                            first[++L] = (int)flat.size();
+                            load = 0;
+                            target = mean_left();
+                            continue;
+                        }
+                        take = std::min(rem, kMinBatchChunk);
+                    } else if (rem - take < kMinBatchChunk) {
+                        // a split here would leave too short a piece: split
+                        // earlier (short of the target) or take it all (past it)
+                        const double under = room - (rem - kMinBatchChunk), over = rem - room;
+                        take = (rem - kMinBatchChunk >= kMinBatchChunk && under < over)
+                                   ? rem - kMinBatchChunk
+                                   : rem;
+                    }
+                }
+                flat.push_back(BatchItem{c.box, c.x0, c.y0, z, z + take});
+                load += take + 2 * kR;
+                left -= take + (first_piece ? 2 * kR : 0);
+                first_piece = false;
+                z += take;
+                if (L < G - 1 && (double)load >= target - 0.5) {
+                    first[++L] = (int)flat.size();
+                    load = 0;
+                    target = mean_left();
+                }
+            }
+        }
+        for (int k = L + 1; k <= G; ++k) first[k] = (int)flat.size();
+        if ((long long)flat.size() > b->items_cap) {
+            b->err = "work list larger than the workspace's item capacity";
+            return FD6_EUNSUPPORTED;
+        }
+    }
+    HIPCHK(b, hipMemcpyAsync(b->items_dev, flat.data(), sizeof(BatchItem) * flat.size(),
+                             hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipMemcpyAsync(b->wg_first_dev, first.data(), sizeof(int) * first.size(),
                              hipMemcpyHostToDevice, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));
-    long long gsz = (long long)cus * per_cu;
-    gsz = std::min<long long>(gsz, (long long)sorted.size());
-    if (gsz >= 8) gsz = gsz / 8 * 8;
     b->tile = tile;
     b->zchunk = zchunk;
-    b->nitems = (int)sorted.size();
-    b->grid = (int)std::max<long long>(gsz, 1);
+    b->nitems = (int)flat.size();
+    b->grid = (int)first.size() - 1;
     b->drop_graphs();
     return FD6_OK;
 }
@@ -784,7 +882,7 @@ int batch_substeps(fd6_batch* b, hipStream_t st, int parity) {
     auto launch = b->aos ? launch_batch55_aos<T, TW> : launch_batch55<T, TW>;
     for (int s = 0; s < 3; ++s) {
         HIPCHK(b, launch(static_cast<const BatchBox<T, TW>*>(b->boxes_dev), b->items_dev,
-                         b->nitems, b->grid, parity, s + 1, b->tile, TW(kAlpha[s]),
+                         b->wg_first_dev, b->grid, parity, s + 1, b->tile, TW(kAlpha[s]),
                          TW(kBeta[s]), st));
         parity ^= 1;
     }
@@ -907,7 +1005,7 @@ int batch_reduce(fd6_batch* b, fd6_reductions* out) {
 
 // ---- ensemble autotuner ----------------------------------------------------
 // Candidate z-chunk lengths (0: whole boxes) and timed steps per candidate.
-constexpr int kBatchTuneChunks[] = {0, 32, 48, 64};
+constexpr int kBatchTuneChunks[] = {0, 32, 48, 64, kBatchBalanced};
 constexpr int kBatchTuneSteps = 3;
 
 // Two timing events, destroyed with the scope.
@@ -1401,6 +1499,7 @@ int fd6_batch_create(int32_t n, const fd6_desc* descs, void* d_ws, size_t bytes,
         b->boxes_dev = b->ws + bp.off_boxes;
         b->box_bytes = bp.box_bytes;
         b->items_dev = reinterpret_cast<BatchItem*>(b->ws + bp.off_items);
+        b->wg_first_dev = reinterpret_cast<int*>(b->ws + bp.off_wg);
         b->items_cap = bp.items_cap;
         b->partials = reinterpret_cast<double*>(b->ws + bp.off_partials);
         b->results = reinterpret_cast<double*>(b->ws + bp.off_results);
@@ -1457,7 +1556,7 @@ int fd6_batch_init_fields(fd6_batch* b, int32_t box, const double* lnrho, const 
 
 int fd6_batch_set_schedule(fd6_batch* b, int32_t tile, int32_t zchunk) {
     int tx, ty;
-    if (!b || zchunk < 0 || (zchunk > 0 && zchunk < kMinBatchChunk) ||
+    if (!b || (zchunk != kBatchBalanced && (zchunk < 0 || (zchunk > 0 && zchunk < kMinBatchChunk))) ||
         substep55_tile_dims(tile, &tx, &ty))
         return FD6_EINVAL;
     if (b->aos && !substep55_aos_tile_ok(tile)) return FD6_EUNSUPPORTED;

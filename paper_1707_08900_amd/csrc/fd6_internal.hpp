@@ -160,19 +160,22 @@ struct BatchBox {
 struct BatchItem {
     int box, x0, y0, zb, ze;
 };
+// Workgroups of a batched launch: the persistent grid never exceeds this, so
+// the per-workgroup list offsets fit a fixed slot in the workspace.
+constexpr int kMaxBatchGrid = 65536;
 // Tile extents of a z-sweep kernel shape (tile >= 1); -1 for other shapes.
 int substep55_tile_dims(int tile, int* tx, int* ty);
 template <typename T, typename TW>
-hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
-                          int grid, int parity, int s, int tile, TW alpha, TW beta,
-                          hipStream_t st);
+hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items,
+                          const int* wg_first, int grid, int parity, int s, int tile, TW alpha,
+                          TW beta, hipStream_t st);
 template <typename T, typename TW>
 int batch55_blocks_per_cu(int tile);
 // The same for ensembles whose boxes all use the array-of-structures layout.
 template <typename T, typename TW>
-hipError_t launch_batch55_aos(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
-                              int grid, int parity, int s, int tile, TW alpha, TW beta,
-                              hipStream_t st);
+hipError_t launch_batch55_aos(const BatchBox<T, TW>* boxes, const BatchItem* items,
+                              const int* wg_first, int grid, int parity, int s, int tile,
+                              TW alpha, TW beta, hipStream_t st);
 template <typename T, typename TW>
 int batch55_blocks_per_cu_aos(int tile);
 

@@ -11,7 +11,7 @@ template hipError_t launch_substep55_aos<float, float>(const Geom&, Fields4<floa
                                                    int, int*, const ForceArgs<float>*,
                                                    hipStream_t);
 template hipError_t launch_batch55_aos<float, float>(const BatchBox<float, float>*,
-                                                 const BatchItem*, int, int, int, int, int,
+                                                 const BatchItem*, const int*, int, int, int, int,
                                                  float, float, hipStream_t);
 template int batch55_blocks_per_cu_aos<float, float>(int);
 

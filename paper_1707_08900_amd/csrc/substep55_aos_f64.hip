@@ -11,7 +11,7 @@ template hipError_t launch_substep55_aos<double, double>(const Geom&, Fields4<do
                                                    int, int*, const ForceArgs<double>*,
                                                    hipStream_t);
 template hipError_t launch_batch55_aos<double, double>(const BatchBox<double, double>*,
-                                                 const BatchItem*, int, int, int, int, int,
+                                                 const BatchItem*, const int*, int, int, int, int,
                                                  double, double, hipStream_t);
 template int batch55_blocks_per_cu_aos<double, double>(int);
 

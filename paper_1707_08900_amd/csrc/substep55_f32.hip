@@ -10,7 +10,7 @@ template hipError_t launch_substep55<float, float>(const Geom&, Fields4<float>, 
                                               Fields4<float>, const Coef<float>&,
                                               const RKCoef<float>&, int, int, int, double*, int,
                                               int*, const ForceArgs<float>*, hipStream_t);
-template hipError_t launch_batch55<float, float>(const BatchBox<float, float>*, const BatchItem*, int,
+template hipError_t launch_batch55<float, float>(const BatchBox<float, float>*, const BatchItem*, const int*,
                                             int, int, int, int, float, float, hipStream_t);
 template int batch55_blocks_per_cu<float, float>(int);
 template hipError_t launch_pass19a_sweep<float, float>(const Geom&, Fields4<float>, Fields4<float>,

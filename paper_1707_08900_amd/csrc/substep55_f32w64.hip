@@ -10,7 +10,7 @@ template hipError_t launch_substep55<float, double>(const Geom&, Fields4<float>,
                                               Fields4<double>, const Coef<float>&,
                                               const RKCoef<double>&, int, int, int, double*, int,
                                               int*, const ForceArgs<float>*, hipStream_t);
-template hipError_t launch_batch55<float, double>(const BatchBox<float, double>*, const BatchItem*, int,
+template hipError_t launch_batch55<float, double>(const BatchBox<float, double>*, const BatchItem*, const int*,
                                             int, int, int, int, double, double, hipStream_t);
 template int batch55_blocks_per_cu<float, double>(int);
 template hipError_t launch_pass19a_sweep<float, double>(const Geom&, Fields4<float>, Fields4<float>,

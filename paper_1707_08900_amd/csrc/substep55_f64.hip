@@ -10,7 +10,7 @@ template hipError_t launch_substep55<double, double>(const Geom&, Fields4<double
                                               Fields4<double>, const Coef<double>&,
                                               const RKCoef<double>&, int, int, int, double*, int,
                                               int*, const ForceArgs<double>*, hipStream_t);
-template hipError_t launch_batch55<double, double>(const BatchBox<double, double>*, const BatchItem*, int,
+template hipError_t launch_batch55<double, double>(const BatchBox<double, double>*, const BatchItem*, const int*,
                                             int, int, int, int, double, double, hipStream_t);
 template int batch55_blocks_per_cu<double, double>(int);
 template hipError_t launch_pass19a_sweep<double, double>(const Geom&, Fields4<double>, Fields4<double>,

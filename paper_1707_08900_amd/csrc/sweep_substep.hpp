@@ -659,23 +659,25 @@ void substep19_pass1(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, T* dv
 }
 
 // Batched form: one persistent launch advances every box of an ensemble by
-// one substep.  The host lists the tile-chunks of all boxes (longest first);
-// workgroup b takes list entries remap(b), remap(b) + G, ... where the remap
-// gives each XCD a contiguous run of the list, so that tiles of one box share
-// that XCD's L2.  Per-box geometry, pointers, coefficients and time step come
-// from device memory, so a captured graph never needs re-capture when they
-// change.  Per point the arithmetic is the single-box kernel's.
+// one substep.  The host gives every workgroup its own list of tile-chunks
+// (items wg_first[L] .. wg_first[L + 1] - 1), where L = remap(blockIdx) numbers
+// the workgroups of one XCD contiguously, so that the host can hand one XCD
+// neighbouring tiles of the same boxes and they share its L2.  Per-box
+// geometry, pointers, coefficients and time step come from device memory, so
+// a captured graph never needs re-capture when they change.  Per point the
+// arithmetic is the single-box kernel's.
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS>
 __global__ __launch_bounds__(TX* TY)
 void substep55_batch(const BatchBox<T, TW>* __restrict__ boxes,
-                     const BatchItem* __restrict__ items, int nitems, int parity, TW alpha,
-                     TW beta) {
+                     const BatchItem* __restrict__ items, const int* __restrict__ wg_first,
+                     int parity, TW alpha, TW beta) {
     using Sh = SweepShape<T, TX, TY, LD>;
     __shared__ T lds[2 * 4 * Sh::FS];
     const int G = gridDim.x;
     int b = blockIdx.x;
     if ((G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3);
-    for (int it = b; it < nitems; it += G) {
+    const int last = wg_first[b + 1];
+    for (int it = wg_first[b]; it < last; ++it) {
         const BatchItem wi = items[it];
         const BatchBox<T, TW>* bx = boxes + wi.box;
         const Geom g = bx->g;
@@ -831,16 +833,16 @@ hipError_t launch_pass19a_sweep(const Geom& g, Fields4<T> in, Fields4<T> out, Fi
 namespace {
 
 template <typename T, typename TW, int VS>
-hipError_t launch_batch55_vs(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
-                             int grid, int parity, int s, int tile, TW alpha, TW beta,
-                             hipStream_t st) {
+hipError_t launch_batch55_vs(const BatchBox<T, TW>* boxes, const BatchItem* items,
+                             const int* wg_first, int grid, int parity, int s, int tile, TW alpha,
+                             TW beta, hipStream_t st) {
     return with_tile(tile, hipErrorInvalidValue, [&](auto I) -> hipError_t {
         constexpr TileCfg k = kTiles[decltype(I)::value];
         if constexpr (k.tx == 0 || (VS != 1 && k.ld)) {
             return hipErrorInvalidValue;
         } else {
             return launch_s<KBatch<T, TW, k.tx, k.ty, k.pd, k.ld, k.nt, VS>::template at>(
-                s, dim3(grid), dim3(k.tx * k.ty), st, boxes, items, nitems, parity, alpha, beta);
+                s, dim3(grid), dim3(k.tx * k.ty), st, boxes, items, wg_first, parity, alpha, beta);
         }
     });
 }
@@ -865,19 +867,19 @@ int batch55_blocks_per_cu_vs(int tile) {
 }  // namespace
 
 template <typename T, typename TW>
-hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
-                          int grid, int parity, int s, int tile, TW alpha, TW beta,
-                          hipStream_t st) {
-    return launch_batch55_vs<T, TW, 1>(boxes, items, nitems, grid, parity, s, tile, alpha, beta,
-                                       st);
+hipError_t launch_batch55(const BatchBox<T, TW>* boxes, const BatchItem* items,
+                          const int* wg_first, int grid, int parity, int s, int tile, TW alpha,
+                          TW beta, hipStream_t st) {
+    return launch_batch55_vs<T, TW, 1>(boxes, items, wg_first, grid, parity, s, tile, alpha,
+                                       beta, st);
 }
 
 template <typename T, typename TW>
-hipError_t launch_batch55_aos(const BatchBox<T, TW>* boxes, const BatchItem* items, int nitems,
-                              int grid, int parity, int s, int tile, TW alpha, TW beta,
-                              hipStream_t st) {
-    return launch_batch55_vs<T, TW, 4>(boxes, items, nitems, grid, parity, s, tile, alpha, beta,
-                                       st);
+hipError_t launch_batch55_aos(const BatchBox<T, TW>* boxes, const BatchItem* items,
+                              const int* wg_first, int grid, int parity, int s, int tile,
+                              TW alpha, TW beta, hipStream_t st) {
+    return launch_batch55_vs<T, TW, 4>(boxes, items, wg_first, grid, parity, s, tile, alpha,
+                                       beta, st);
 }
 
 template <typename T, typename TW>

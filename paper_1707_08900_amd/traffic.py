@@ -5,8 +5,9 @@ same command write per-dispatch counter values in KiB.  The command also runs
 a plain 1 GiB device copy (bench.py --calibrate-copy), whose true traffic is
 1 GiB read and 1 GiB written; the ratio to what the counters report for it is
 the scale applied to every kernel's values.  This module turns the two CSV
-files into per-kernel bytes per dispatch, and writes the record bench.py
-reads for its roofline's `traffic`.
+files into per-kernel bytes per dispatch, and adds (or replaces) the record
+of that kernel shape, z-chunk and layout in the file bench.py reads for its
+roofline's `traffic`.
 
     python -m paper_1707_08900_amd.traffic FETCH_DIR WRITE_DIR --match substep55_sweep \\
         --alg-bytes-per-launch 7158278826.67 [--record profiles/traffic_....json ...]
@@ -95,8 +96,17 @@ def main(argv=None):
         for kv in a.record_field:
             k, v = kv.split("=", 1)
             rec[k] = int(v) if v.lstrip("-").isdigit() else v
+        # one record per (kernel shape, z-chunk, layout): replace that one
+        try:
+            with open(a.record) as f:
+                doc = json.load(f)
+            records = doc.get("records", []) if isinstance(doc, dict) else []
+        except (OSError, ValueError):
+            records = []
+        key = lambda r: (r.get("tile"), r.get("zchunk"), r.get("layout"))  # noqa: E731
+        records = [r for r in records if key(r) != key(rec)] + [rec]
         with open(a.record, "w") as f:
-            json.dump(rec, f, indent=1)
+            json.dump({"records": records}, f, indent=1)
             f.write("\n")
         print(f"record written to {a.record}")
     return 0

@@ -110,7 +110,7 @@ def test_acc64_removes_the_fp32_rounding_of_dt(fd6, orc):
             res[(name, prec)] = rms_err(out, ref)
     print("64^3 x 100 steps, RMS error vs oracle: " +
           ", ".join(f"{k[1]} {k[0]} {v:.3e}" for k, v in res.items()), flush=True)
-    assert abs(np.float32(w.dt) - w.dt) / w.dt > 4e-8
+    assert abs(float(np.float32(w.dt)) - w.dt) / w.dt > 4e-8
     assert res[("dt", "fp32_acc64")] * 1.8 <= res[("dt", "fp32")]
     assert res[("dt32", "fp32")] * 2 <= res[("dt", "fp32")]
     assert abs(res[("dt32", "fp32_acc64")] / res[("dt", "fp32_acc64")] - 1) < 0.05
