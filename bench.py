@@ -181,7 +181,7 @@ def timed_steps(torch, box, red, steps, warmup, timing=True):
 
 
 def run_form(torch, fd6, w, dev_fields, prec, var, layout, steps, warmup, tile=None, zchunk=0,
-             graph=False, error_steps=1):
+             graph=False, error_steps=1, fused12=False):
     """Tune (or fix) the schedule, time `steps` reducing steps after `warmup`,
     then run `error_steps` steps from the initial state in the same schedule
     and return the state (FP64 device tensors) for the error check."""
@@ -196,11 +196,12 @@ def run_form(torch, fd6, w, dev_fields, prec, var, layout, steps, warmup, tile=N
         box.set_tile(tile)
         box.set_zchunk(zchunk)
         tuned = {"tile": tile, "zchunk": zchunk}
+    box.set_fused_substeps(fused12)
     box.init_fields(dev_fields)
     red = torch.zeros(8, dtype=torch.float64, device="cuda")
     wall, ev_ms, (kms, klaunch, gms, glaunch) = timed_steps(torch, box, red, steps, warmup)
     v = n3 * steps / (ev_ms * 1e-3)
-    alg_launch = n3 * ALG_BYTES[(var, prec)] / LAUNCHES[var]
+    alg_launch = n3 * ALG_BYTES[(var, prec)] / (2 if fused12 else LAUNCHES[var])
     avg_launch_s = kms * 1e-3 / klaunch
     res = {"updates_per_s": v, "ms_per_step": ev_ms / steps,
            "hbm_frac_step": v * ALG_BYTES[(var, prec)] / (HBM_PEAK_GBS * 1e9),
@@ -443,6 +444,9 @@ def main():
                     help="precision form of the headline box (profiling the other forms)")
     ap.add_argument("--variant", choices=("55p", "19p"), default="55p",
                     help="method of the headline box (profiling the other forms)")
+    ap.add_argument("--fused12", action="store_true",
+                    help="headline box with substeps 1 and 2 fused in one launch (FP32, "
+                         "55-point; profiling the temporal-blocking schedule)")
     a = ap.parse_args()
     if a.variant == "19p":
         a.layout = "soa"  # the 19-point passes keep one array per field
@@ -486,7 +490,7 @@ def main():
     hk = "fp32" if (prec, var, n) == ("fp32", "55p", 512) else "headline"
     head, hx, hout = run_form(torch, fd6, w, dev_fields, prec, var, a.layout, a.steps, a.warmup,
                               tile=a.tile, zchunk=a.zchunk, graph=True,
-                              error_steps=0 if a.no_check else 1)
+                              error_steps=0 if a.no_check else 1, fused12=a.fused12)
     tuned = hx["tuned"]
     log(f"kernel shape: {tuned}")
     ms_per_step = head["ms_per_step"]
@@ -496,14 +500,16 @@ def main():
 
     # dominant kernel: the fused 55-point substep kernel (19-point: the
     # average of its two passes)
-    alg_per_launch = n ** 3 * ALG_BYTES[(var, prec)] / LAUNCHES[var]
+    alg_per_launch = n ** 3 * ALG_BYTES[(var, prec)] / (2 if a.fused12 else LAUNCHES[var])
     avg_launch_s = hx["kms"] * 1e-3 / hx["klaunch"]
     achieved = alg_per_launch / avg_launch_s / 1e9
     traffic = load_traffic(tuned, a.layout, var, prec, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
-                "kernel": (f"substep55_sweep (fused RHS + RK3, {a.layout} layout)" if var == "55p"
+                "kernel": ("substep55_fused12 + substep55_sweep_red (average per launch)"
+                           if a.fused12 else
+                           f"substep55_sweep (fused RHS + RK3, {a.layout} layout)" if var == "55p"
                            else "substep19_pass1 / substep19_pass2 (average per launch)"),
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": hx["klaunch"],
                 "alg_bytes_per_launch": alg_per_launch,

@@ -240,6 +240,21 @@ typedef struct {
 } fd6_forcing;
 int fd6_set_forcing(fd6_box *box, const fd6_forcing *f);
 
+/* Temporal blocking of substeps 1 and 2 (the paper's discussion of Sec. 7
+ * proposes it): with enable != 0 every step runs substeps 1 and 2 as ONE
+ * launch in which a workgroup sweeps substep 1 over its 16 x 16 output tile
+ * and a 3-column ring, keeps that substep's new state and RK3 register on
+ * chip (LDS), and sweeps substep 2 of the tile from them; substep 3 follows
+ * as usual.  The substep-1 state and register never reach HBM (112 -> 48
+ * bytes per point for the two substeps, FP32), at the price of substep 1 on
+ * 22 x 22 / (16 x 16) = 1.9 times the columns.  Results are bit for bit
+ * those of the plain launches.  An experimental schedule, off by default:
+ * the plain launches are faster on MI355X (the fused kernel is bound by its
+ * arithmetic and by the registers two column states need).  FP32 precision
+ * and the 55-point method only (FD6_EUNSUPPORTED otherwise); ignored while a
+ * force is set.  Drops captured steps when it changes. */
+int fd6_set_fused_substeps(fd6_box *box, int32_t enable);
+
 /* Graph mode (Algorithm 2 as one HIP graph per step): with enable != 0,
  * fd6_rk3_step and fd6_rk3_step_reduce capture one full step (three substeps,
  * and for the reducing variant the diagnostics of the last step, with d_out

@@ -40,7 +40,7 @@ ABI_SYMBOLS = (
     "fd6_rk3_step", "fd6_rk3_step_reduce", "fd6_get_fields", "fd6_get_fields_device", "fd6_reduce", "fd6_rhs",
     "fd6_reduce_device", "fd6_tile_count", "fd6_set_tile", "fd6_set_zchunk", "fd6_set_graph",
     "fd6_get_schedule", "fd6_tune", "fd6_get_tune_log",
-    "fd6_set_forcing", "fd6_set_timing",
+    "fd6_set_forcing", "fd6_set_timing", "fd6_set_fused_substeps",
     "fd6_get_timing",
     "fd6_last_error", "fd6_batch_workspace_bytes", "fd6_batch_create", "fd6_batch_destroy",
     "fd6_batch_set_params", "fd6_batch_init_fields", "fd6_batch_set_schedule",
@@ -105,6 +105,7 @@ def _declare(lib):
         "fd6_set_tile": (I, [P, ctypes.c_int32]),
         "fd6_set_zchunk": (I, [P, ctypes.c_int32]),
         "fd6_set_graph": (I, [P, ctypes.c_int32]),
+        "fd6_set_fused_substeps": (I, [P, ctypes.c_int32]),
         "fd6_set_forcing": (I, [P, ctypes.POINTER(Fd6Forcing)]),
         "fd6_last_error": (ctypes.c_char_p, [P]),
         "fd6_batch_workspace_bytes": (I, [ctypes.c_int32, ctypes.POINTER(Fd6Desc),
@@ -338,6 +339,12 @@ class Box:
         f = Fd6Forcing(*[float(v) for v in forcing["k"]], *[float(v) for v in forcing["e"]],
                        float(forcing["f0"]), float(forcing["phase"]))
         self._check(self.lib.fd6_set_forcing(self.h, ctypes.byref(f)), "fd6_set_forcing")
+
+    def set_fused_substeps(self, enable: bool):
+        """Run substeps 1 and 2 of every step as one launch (temporal
+        blocking; FP32, 55-point; experimental, off by default)."""
+        self._check(self.lib.fd6_set_fused_substeps(self.h, 1 if enable else 0),
+                    "fd6_set_fused_substeps")
 
     def set_graph(self, enable: bool):
         """Replay each step as a captured HIP graph."""

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfd6.so")
 SOURCES = ["aux_kernels.hip", "substep55_f32.hip", "substep55_f64.hip", "substep55_f32w64.hip",
            "substep55_aos_f32.hip", "substep55_aos_f64.hip", "substep55_aos_f32w64.hip",
-           "substep19.hip", "reduce_static.hip", "fd6_abi.cpp"]
+           "substep19.hip", "reduce_static.hip", "fused12_f32.hip", "fd6_abi.cpp"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

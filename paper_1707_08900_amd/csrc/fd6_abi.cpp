@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <type_traits>
 #include <algorithm>
 #include <array>
 #include <new>
@@ -68,6 +69,8 @@ struct fd6_box {
     // optional captured graphs of one full step, per starting parity; the
     // reducing variant also records its diagnostics target
     bool use_graph = false;
+    // substeps 1 and 2 of a step in one launch (FP32, 55-point, no force)
+    bool fused12 = false;
     hipStream_t cap = nullptr;  // private stream used only for graph capture
     hipGraphExec_t gstep[2] = {nullptr, nullptr};
     hipGraphExec_t gred[2] = {nullptr, nullptr};
@@ -423,12 +426,47 @@ int force_sync(fd6_box* b) {
     return FD6_OK;
 }
 
+// Whether a step runs substeps 1 and 2 as one fused launch (fd6_set_fused_substeps).
+bool fused_step(const fd6_box* b) { return b->fused12 && !b->force_on; }
+
+// Substeps 1 and 2 in one launch: state[cur] -> state[cur ^ 1], w holding
+// the substep-2 register (one in/out swap instead of two).
+template <typename T, typename TW>
+int fused12_substeps(fd6_box* b) {
+    if constexpr (!std::is_same<T, float>::value || !std::is_same<TW, float>::value) {
+        b->err = "fused substeps: FP32 state and register only";
+        return FD6_EUNSUPPORTED;
+    } else {
+        const double dt = b->params.dt;
+        const RKCoef<TW> rk1{TW(kAlpha[0]), TW(kBeta[0]), TW(dt)};
+        const RKCoef<TW> rk2{TW(kAlpha[1]), TW(kBeta[1]), TW(dt)};
+        const Coef<T> c = make_coef<T>(b->params);
+        int rc = timed(b, b->ev_kernel, [&]() -> int {
+            HIPCHK(b, (launch_fused12<T, TW>(b->geom, fields_of<T>(b->state[b->cur]),
+                                             fields_of<T>(b->state[b->cur ^ 1]),
+                                             fields_of<TW>(b->w), c, rk1, rk2, b->zchunk,
+                                             b->stream)));
+            return FD6_OK;
+        });
+        if (rc) return rc;
+        b->ghosts_ok[b->cur ^ 1] = false;
+        b->cur ^= 1;
+        return FD6_OK;
+    }
+}
+
 // One full step (Algorithm 2: three substeps); red_out != nullptr also
 // produces the diagnostics of the new state.
 template <typename T, typename TW>
 int one_step(fd6_box* b, double* red_out) {
     const double dt = b->params.dt;
-    for (int s = 0; s < 3; ++s) {
+    int s0 = 0;
+    if (fused_step(b)) {
+        int rc = fused12_substeps<T, TW>(b);
+        if (rc) return rc;
+        s0 = 2;
+    }
+    for (int s = s0; s < 3; ++s) {
         RKCoef<TW> rk{TW(kAlpha[s]), TW(kBeta[s]), TW(dt)};
         int rc = do_substep<T, TW>(b, s + 1, rk, red_out);
         if (rc) return rc;
@@ -491,7 +529,7 @@ int do_steps(fd6_box* b, int nsteps, double* red_out = nullptr) {
             if (red) b->gred_out[p] = red_out;
         }
         HIPCHK(b, hipGraphLaunch(*x, b->stream));
-        b->cur ^= 1;  // three in/out swaps
+        if (!fused_step(b)) b->cur ^= 1;  // three in/out swaps (two when fused)
         b->ghosts_ok[0] = b->ghosts_ok[1] = false;
     }
     return FD6_OK;
@@ -1355,6 +1393,15 @@ int fd6_set_tile(fd6_box* b, int32_t tile) {
     if (b->geom.vs == 4 && !substep55_aos_tile_ok(tile)) return FD6_EUNSUPPORTED;
     if (tile != b->tile) b->drop_graphs();
     b->tile = tile;
+    return FD6_OK;
+}
+
+int fd6_set_fused_substeps(fd6_box* b, int32_t enable) {
+    if (!b) return FD6_EINVAL;
+    if (enable && (b->desc.precision != FD6_FP32 || b->desc.variant != FD6_55P))
+        return FD6_EUNSUPPORTED;
+    if ((enable != 0) != b->fused12) b->drop_graphs();
+    b->fused12 = enable != 0;
     return FD6_OK;
 }
 

@@ -143,6 +143,13 @@ hipError_t launch_substep55_aos(const Geom& g, Fields4<T> in, Fields4<T> out, Fi
                                 int zchunk, double* partials, int part_cap, int* nparts,
                                 const ForceArgs<T>* frc, hipStream_t st);
 bool substep55_aos_tile_ok(int tile);
+// Substeps 1 and 2 of one step in a single launch (FP32 state and register,
+// either layout): in -> out after both substeps, w holding the substep-2
+// register.  rk1, rk2: the two substeps' coefficients.
+template <typename T, typename TW>
+hipError_t launch_fused12(const Geom& g, Fields4<T> in, Fields4<T> out, Fields4<TW> w,
+                          const Coef<T>& c, const RKCoef<TW>& rk1, const RKCoef<TW>& rk2,
+                          int zchunk, hipStream_t st);
 // Whether a kernel shape reads the ghost zone of its input (the z-sweep
 // shapes resolve the periodic images in their loader instead).
 bool substep55_reads_ghosts(int tile);

@@ -148,8 +148,11 @@ struct SweepCtx {
 // zone.  Cells beyond x < nx + 3, y < ny + 3 never feed a stored point and are
 // dropped.
 // VS: values per point in memory (1, or 4 for the array-of-structures
-// layout); all byte offsets and plane sizes scale with it.
-template <typename T, typename TW, int TX, int TY, bool LD, int VS = 1>
+// layout); all byte offsets and plane sizes scale with it.  WRAP_ALL: every
+// cell at any offset takes its periodic image and none is dropped (the
+// extended tile of the substep-1+2 fusion, whose cells may lie a whole tile
+// beyond the box).
+template <typename T, typename TW, int TX, int TY, bool LD, int VS = 1, bool WRAP_ALL = false>
 __device__ __forceinline__ void sweep_ctx_init(SweepCtx<T, TX, TY, LD>& X, const Geom& g, int x0,
                                                int y0) {
     using Sh = SweepShape<T, TX, TY, LD>;
@@ -159,6 +162,10 @@ __device__ __forceinline__ void sweep_ctx_init(SweepCtx<T, TX, TY, LD>& X, const
     X.plane_bytes = (unsigned)(g.plane * (long long)PT);
     X.wplane_bytes = (unsigned)(g.wplane * (long long)PW);
     auto wrapped_off = [&](int gx, int gy) -> unsigned {  // gx, gy in [-3, ...)
+        if constexpr (WRAP_ALL) {
+            const int ix = ((gx % g.nx) + g.nx) % g.nx, iy = ((gy % g.ny) + g.ny) % g.ny;
+            return (unsigned)(((iy + kR) * g.px + (ix + kR)) * PT);
+        }
         if (gx >= g.nx + kR || gy >= g.ny + kR) return kDropOffset;
         const int ix = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
         const int iy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);

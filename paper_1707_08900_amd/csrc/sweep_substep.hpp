@@ -244,21 +244,30 @@ __device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
     }
 }
 
+// TB selects the two stages of the substep-1+2 fusion (fused12_tile): 0 is
+// the plain sweep; 1 is substep 1 over the extended region, whose new state
+// goes to the LDS plane buffer tb_u (layout of the inner tile's sweep) and
+// whose RK3 register, for the inner columns, to the LDS ring tb_w; 2 is
+// substep 2 of the inner tile, which takes its plane from tb_u (passed as
+// lds, loaded by stage 1) and its RK3 register from tb_w, and starts output
+// planes 2 * kR steps later.
 template <int PH, int S, int PD, bool LD, bool NT, int VS, bool P19, bool RED, bool FRC,
-          typename T, typename TW, int TX, int TY, int NH>
+          int TB = 0, typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, TW, NH>& R,
                                            const SweepCtx<T, TX, TY, LD>& X, T* lds,
                                            lds_t<T> lds3, const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
                                            const Coef<T>& cf, const RKCoef<TW>& rk,
-                                           const T* ftab) {
+                                           const T* ftab, T* tb_u = nullptr,
+                                           TW* tb_w = nullptr) {
     using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int W = Sh::W;
+    static_assert(TB == 0 || (!LD && !P19 && !RED && !FRC), "fusion: plain register sweep only");
     const int t = t0 + PH;
     if (t >= nplanes) return;
     const int p = zb - kR + t;  // plane loaded in this step
     const int o = p - kR;       // output plane finished in this step
-    const bool outstep = t >= 2 * kR;
+    const bool outstep = t >= (TB == 2 ? 4 : 2) * kR;
 
     T* buf = lds + (PH & 1) * 4 * Sh::FS;
     const int ci = (threadIdx.x / TX + kR) * W + (threadIdx.x % TX + kR);
@@ -267,7 +276,9 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     static_assert(PD == 1 || PD == 2 || PD == 4, "prefetch depth");
     constexpr int RS = PH % PD;
     constexpr int WS = PD >= 2 ? (PH & 1) : 0;
-    if constexpr (!LD) {
+    if constexpr (TB == 2) {
+        // plane p was written to LDS by stage 1 of this step (barrier between)
+    } else if constexpr (!LD) {
         // RK3 register of an output point, issued early: PD = 1 loads the one
         // finished in this step, PD = 2 the one finished in the next step
         if constexpr (S != 1) {
@@ -390,17 +401,31 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
         TW wout[4];
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-            TW wv = S == 1 ? TW(0) : R.wq[WS][f];
+            // stage 2 of the fusion: the register stage 1 wrote 3 steps earlier
+            TW wv = S == 1 ? TW(0)
+                           : (TB == 2 ? tb_w[((PH + 1) & 3) * 4 * (TX * TY) + f * (TX * TY) +
+                                             threadIdx.x]
+                                      : R.wq[WS][f]);
             const T v = rk_update<S>(R.q[f][sl8(PH - 3)], r[f], wv, rk);
             vout[f] = v;
             wout[f] = wv;
-            if constexpr (VS == 1) {
+            if constexpr (TB == 1) {
+                // new state of every extended column into the inner sweep's
+                // plane buffer (its cell is this thread's index); the register
+                // of the inner columns into ring slot (step & 3)
+                constexpr int NI = (TX - 2 * kR) * (TY - 2 * kR);
+                constexpr int FS2 = SweepShape<T, TX - 2 * kR, TY - 2 * kR>::FS;
+                tb_u[(PH & 1) * 4 * FS2 + f * FS2 + threadIdx.x] = v;
+                const int ix = (int)(threadIdx.x % TX) - kR, iy = (int)(threadIdx.x / TX) - kR;
+                if (ix >= 0 && ix < TX - 2 * kR && iy >= 0 && iy < TY - 2 * kR)
+                    tb_w[(PH & 3) * 4 * NI + f * NI + iy * (TX - 2 * kR) + ix] = wv;
+            } else if constexpr (VS == 1) {
                 bstore<CP>(v, plane_rsrc(out.f[f] + ocorner, ob), X.lane_o);
                 if constexpr (S != 3)
                     bstore<CP>(wv, plane_rsrc(w.f[f] + (long long)o * g.wplane, wb), X.lane_w);
             }
         }
-        if constexpr (VS == 4) {
+        if constexpr (VS == 4 && TB != 1) {
             bstore_point<CP>(vout, plane_rsrc(out.f[0] + 4 * ocorner, ob), X.lane_o);
             if constexpr (S != 3)
                 bstore_point<CP>(wout, plane_rsrc(w.f[0] + 4 * (long long)o * g.wplane, wb),
@@ -627,6 +652,97 @@ void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<
     if (t.zb >= t.ze) return;
     sweep_tile<T, TW, TX, TY, S, PD, LD, NT, VS, false, false, FRC>(
         g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
+}
+
+// Substeps 1 and 2 of one step in one launch: the temporal blocking the
+// paper's discussion of Sec. 7 proposes, in the z-sweep.  A workgroup of
+// (TX + 6) x (TY + 6) threads owns a TX x TY output tile.
+//  * Stage 1: the substep-1 sweep over the extended tile (the output tile
+//    and a 3-column ring), one column per thread, loading the input state as
+//    the plain sweep does.  Its new state does not go to memory: plane o1
+//    goes into an LDS plane buffer laid out as the inner tile's sweep reads
+//    its planes, and the RK3 register of the inner columns into an LDS ring
+//    of 4 planes.
+//  * Stage 2 (threads 0 .. TX TY - 1, whole waves): the substep-2 sweep of
+//    the output tile with that buffer as its plane source, 3 planes behind
+//    stage 1, storing the substep-2 state and RK3 register.
+// The substep-1 state and register never reach HBM: substeps 1 and 2 move
+// 16 + 32 bytes per point (FP32) instead of 48 + 64, at the price of
+// substep 1 on (TX + 6)(TY + 6) / (TX TY) times the columns.  Per point the
+// arithmetic is the plain sweep's, so the result is bit for bit that of two
+// plain launches.  The loaded planes start 2 * kR further back (nplanes =
+// chunk + 4 kR).
+template <typename T, typename TW, int TX, int TY, int PD, bool NT, int VS>
+__device__ __forceinline__ void fused12_tile(const Geom& g, const Fields4<T>& in,
+                                             const Fields4<T>& out, const Fields4<TW>& w,
+                                             const Coef<T>& cf, const RKCoef<TW>& rk1,
+                                             const RKCoef<TW>& rk2, int x0, int y0, int zb,
+                                             int ze, T* lds1, T* lds2, TW* ring) {
+    constexpr int EX = TX + 2 * kR, EY = TY + 2 * kR;
+    using Sh1 = SweepShape<T, EX, EY>;
+    using Sh2 = SweepShape<T, TX, TY>;
+    static_assert(Sh2::W == EX && Sh2::H == EY, "stage-2 planes are the stage-1 tile");
+    static_assert((TX * TY) % 64 == 0, "stage 2 runs on whole waves");
+    SweepCtx<T, EX, EY> X1;
+    sweep_ctx_init<T, TW, EX, EY, false, VS, true>(X1, g, x0 - kR, y0 - kR);
+    SweepCtx<T, TX, TY> X2;
+    const bool inner = threadIdx.x < TX * TY;
+    if (inner) sweep_ctx_init<T, TW, TX, TY, false, VS>(X2, g, x0, y0);
+    SweepRegs<T, TW, Sh1::NH> R1;
+    SweepRegs<T, TW, Sh2::NH> R2;
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            R1.q[f][s] = R2.q[f][s] = T(0);
+            R1.dd[s >> 1][(2 * f + (s & 1))] = R2.dd[s >> 1][(2 * f + (s & 1))] = T(0);
+        }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) R1.L[i][s] = R2.L[i][s] = T(0);
+    const int nplanes = (ze - zb) + 4 * kR;
+    const int zb1 = zb - kR, zb2 = zb - 2 * kR;  // stage 1 outputs from zb - 3
+    sweep_prefetch<0, VS>(R1, X1, in, plane_corner(g, zb1 - kR), X1.plane_bytes);
+    if constexpr (PD >= 2)
+        sweep_prefetch<1, VS>(R1, X1, in, plane_corner(g, zb1 - kR + 1), X1.plane_bytes);
+    static_assert(PD == 1 || PD == 2, "prefetch depth of the fused sweep");
+    const Fields4<T> none{{nullptr, nullptr, nullptr, nullptr}};
+    for (int t0 = 0; t0 < nplanes; t0 += 8) {
+#define FD6_FUSED_STEP(PH)                                                                      \
+        sweep_step<PH, 1, PD, false, NT, VS, false, false, false, 1>(                            \
+            t0, nplanes, zb1, R1, X1, lds1, (lds_t<T>)lds1, g, in, none, w, (T*)nullptr, cf,     \
+            rk1, (const T*)nullptr, lds2, ring);                                                 \
+        __syncthreads();                                                                         \
+        if (inner)                                                                               \
+            sweep_step<PH, 2, PD, false, NT, VS, false, false, false, 2>(                        \
+                t0, nplanes, zb2, R2, X2, lds2, (lds_t<T>)lds2, g, in, out, w, (T*)nullptr, cf,  \
+                rk2, (const T*)nullptr, (T*)nullptr, ring);
+        FD6_FUSED_STEP(0)
+        FD6_FUSED_STEP(1)
+        FD6_FUSED_STEP(2)
+        FD6_FUSED_STEP(3)
+        FD6_FUSED_STEP(4)
+        FD6_FUSED_STEP(5)
+        FD6_FUSED_STEP(6)
+        FD6_FUSED_STEP(7)
+#undef FD6_FUSED_STEP
+    }
+}
+
+template <typename T, typename TW, int TX, int TY, int PD, bool NT, int VS>
+__global__ __launch_bounds__((TX + 2 * kR) * (TY + 2 * kR))
+void substep55_fused12(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
+                       RKCoef<TW> rk1, RKCoef<TW> rk2, SweepGrid m) {
+    using Sh1 = SweepShape<T, TX + 2 * kR, TY + 2 * kR>;
+    using Sh2 = SweepShape<T, TX, TY>;
+    __shared__ T lds1[2 * 4 * Sh1::FS];
+    __shared__ T lds2[2 * 4 * Sh2::FS];
+    __shared__ TW ring[4 * 4 * TX * TY];
+    const TileXY t = sweep_tile_of(g, TX, TY, m);
+    if (t.zb >= t.ze) return;
+    fused12_tile<T, TW, TX, TY, PD, NT, VS>(g, in, out, w, cf, rk1, rk2, t.tx, t.ty, t.zb, t.ze,
+                                            lds1, lds2, ring);
 }
 
 // Substep 3 with the FP64 diagnostics of the new state fused in: one partial

@@ -242,3 +242,48 @@ def test_library_tuner_single_box(fd6, layout, tmp_path):
     for a, b in zip(got, ref.get_fields()):
         assert np.array_equal(a, b)
     ref.close()
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+@pytest.mark.parametrize("shape", [(32, 32, 32), (23, 29, 37), (6, 6, 6), (40, 6, 70)])
+def test_fused_substeps_bitwise_equal_to_plain_launches(fd6, orc, layout, shape):
+    """Substeps 1 and 2 in one launch (temporal blocking): bit for bit the
+    plain launches, with and without the fused diagnostics and in graph
+    replay, on boxes smaller than the 16 x 16 tile and with ragged tails;
+    and within the FP32 bound of the oracle."""
+    import torch
+    w = si.noise_box(shape, seed=31)
+    ref = make(fd6, w, "fp32", layout)
+    ref.step(3)
+    want = ref.get_fields()
+    red_ref = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ref.init_fields(w.fields)
+    ref.step_reduce(2, red_ref)
+    ref.close()
+    box = make(fd6, w, "fp32", layout)
+    box.set_fused_substeps(True)
+    box.step(3)
+    got = box.get_fields()
+    for a, b in zip(got, want):
+        assert np.array_equal(a, b), shape
+    red = torch.zeros(8, dtype=torch.float64, device="cuda")
+    for graph in (False, True):
+        box.set_graph(graph)
+        box.init_fields(w.fields)
+        box.step_reduce(2, red)
+        assert np.array_equal(red.cpu().numpy(), red_ref.cpu().numpy()), graph
+    box.close()
+    ref1 = orc.rk3(si.as_float32_exact(w.fields), w.nu, w.cs, w.dx, w.dy, w.dz, w.dt, "55p", 3)
+    err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(got, ref1))
+    assert err <= 3e-5
+
+
+def test_fused_substeps_refused_where_unsupported(fd6):
+    w = si.noise_box((8, 8, 8), seed=1)
+    for prec, var in (("fp64", "55p"), ("fp32_acc64", "55p"), ("fp32", "19p")):
+        box = fd6.Box(w.shape, prec, var)
+        with pytest.raises(fd6.Fd6Error) as ex:
+            box.set_fused_substeps(True)
+        assert ex.value.status == -6
+        box.set_fused_substeps(False)
+        box.close()
