@@ -252,17 +252,22 @@ __device__ __forceinline__ void sweep_dma(const SweepCtx<T, TX, TY, true>& X,
 // lds, loaded by stage 1) and its RK3 register from tb_w, and starts output
 // planes 2 * kR steps later.
 template <int PH, int S, int PD, bool LD, bool NT, int VS, bool P19, bool RED, bool FRC,
-          int TB = 0, typename T, typename TW, int TX, int TY, int NH>
+          int TB = 0, bool DDL = false, typename T, typename TW, int TX, int TY, int NH>
 __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepRegs<T, TW, NH>& R,
                                            const SweepCtx<T, TX, TY, LD>& X, T* lds,
                                            lds_t<T> lds3, const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
                                            const Coef<T>& cf, const RKCoef<TW>& rk,
                                            const T* ftab, T* tb_u = nullptr,
-                                           TW* tb_w = nullptr) {
+                                           TW* tb_w = nullptr, T* ddl = nullptr) {
     using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int W = Sh::W;
     static_assert(TB == 0 || (!LD && !P19 && !RED && !FRC), "fusion: plain register sweep only");
+    static_assert(!DDL || TB == 0, "LDS derivative slots: plain sweep only");
+    // DDL: the x / y first derivatives of a plane wait for their output in
+    // this thread's LDS slots instead of registers (slot, field pair, thread)
+    using T2 = T __attribute__((ext_vector_type(2)));
+    T2* const dd2 = reinterpret_cast<T2*>(ddl);
     const int t = t0 + PH;
     if (t >= nplanes) return;
     const int p = zb - kR + t;  // plane loaded in this step
@@ -373,10 +378,20 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             Lf[i] = R.L[i][sl8(PH - 3)] + ((i == 2 && !P19) ? cf.sg4[2] : cf.sg[2]) * rz;
         }
         constexpr int DO = (PH + 1) & 3;  // slot of plane p - 3
-        const T gr[3] = {R.dd[DO][0], R.dd[DO][1], dz[0]};
-        const T J[3][3] = {{R.dd[DO][2], R.dd[DO][3], dz[1]},
-                           {R.dd[DO][4], R.dd[DO][5], dz[2]},
-                           {R.dd[DO][6], R.dd[DO][7], dz[3]}};
+        T dxy[8];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            if constexpr (DDL) {
+                const T2 v = dd2[(DO * 4 + f) * Sh::NT + threadIdx.x];
+                dxy[2 * f] = v.x;
+                dxy[2 * f + 1] = v.y;
+            } else {
+                dxy[2 * f] = R.dd[DO][2 * f];
+                dxy[2 * f + 1] = R.dd[DO][2 * f + 1];
+            }
+        }
+        const T gr[3] = {dxy[0], dxy[1], dz[0]};
+        const T J[3][3] = {{dxy[2], dxy[3], dz[1]}, {dxy[4], dxy[5], dz[2]}, {dxy[6], dxy[7], dz[3]}};
         const T u[3] = {R.q[1][sl8(PH - 3)], R.q[2][sl8(PH - 3)], R.q[3][sl8(PH - 3)]};
         T r[4];
         assemble_rhs(u, gr, J, Lf, cf.nu, cf.cs2, r);
@@ -446,10 +461,19 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     // four fields (kept 3 planes), the xy part of the linear viscous term, and
     // the k = 1, 2 terms of the xz / yz stencils of outputs p -+ k.
     // lnrho
-    R.dd[DS][0] = cf.d1[0][0] * (B0[1] - B0[-1]) + cf.d1[0][1] * (B0[2] - B0[-2]) +
-                  cf.d1[0][2] * (B0[3] - B0[-3]);
-    R.dd[DS][1] = cf.d1[1][0] * (B0[W] - B0[-W]) + cf.d1[1][1] * (B0[2 * W] - B0[-2 * W]) +
-                  cf.d1[1][2] * (B0[3 * W] - B0[-3 * W]);
+    auto dd_put = [&](int f, T dx, T dy) {
+        if constexpr (DDL) {
+            dd2[(DS * 4 + f) * Sh::NT + threadIdx.x] = T2{dx, dy};
+        } else {
+            R.dd[DS][2 * f] = dx;
+            R.dd[DS][2 * f + 1] = dy;
+        }
+    };
+    dd_put(0,
+           cf.d1[0][0] * (B0[1] - B0[-1]) + cf.d1[0][1] * (B0[2] - B0[-2]) +
+               cf.d1[0][2] * (B0[3] - B0[-3]),
+           cf.d1[1][0] * (B0[W] - B0[-W]) + cf.d1[1][1] * (B0[2 * W] - B0[-2 * W]) +
+               cf.d1[1][2] * (B0[3 * W] - B0[-3 * W]));
     T lx, ly, lz;  // xy parts of nu (lap u_i + (1/3) d_i div u) at plane p (19-point:
                    // of nu lap u_i)
     T zx[2], zy[2], zz[2];  // scaled k = 1, 2 differences feeding the xz / yz terms
@@ -470,8 +494,8 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
                 m += w2[k - 1] * t;
             }
         }
-        R.dd[DS][2] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
-        R.dd[DS][3] = cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2];
+        dd_put(1, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+               cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
         if constexpr (P19) {
             lx = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
             ly = T(0);
@@ -501,8 +525,8 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
                 m += w2[k - 1] * t;
             }
         }
-        R.dd[DS][4] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
-        R.dd[DS][5] = cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2];
+        dd_put(2, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+               cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
         if constexpr (P19) {
             ly = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
         } else {
@@ -527,8 +551,8 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             rx += w2[k - 1] * (xp + xm);
             ry += w2[k - 1] * (yp + ym);
         }
-        R.dd[DS][6] = cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2];
-        R.dd[DS][7] = cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2];
+        dd_put(3, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+               cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
         lz = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
         if constexpr (!P19) {
 #pragma unroll
@@ -567,13 +591,14 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
 // RED: also reduce the FP64 diagnostics of the output and store this
 // workgroup's partial at part[blockIdx.x * kReduceSlots ...].
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS,
-          bool P19 = false, bool RED = false, bool FRC = false>
+          bool P19 = false, bool RED = false, bool FRC = false, bool DDL = false>
 __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
                                            const Fields4<T>& out, const Fields4<TW>& w, T* dv,
                                            const Coef<T>& cf, const RKCoef<TW>& rk, int x0,
                                            int y0, int zb, int ze, T* lds, lds_t<T> lds3,
                                            double* part = nullptr,
-                                           ForceArgs<T> fa = ForceArgs<T>{nullptr, nullptr}) {
+                                           ForceArgs<T> fa = ForceArgs<T>{nullptr, nullptr},
+                                           T* ddl = nullptr) {
     using Sh = SweepShape<T, TX, TY, LD>;
     constexpr int NH = Sh::NH;
     SweepCtx<T, TX, TY, LD> X;
@@ -595,6 +620,10 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
 #pragma unroll
     for (int i = 0; i < 4; ++i) R.red[i] = 0.0;
     R.bad = 0;
+    if constexpr (DDL) {
+#pragma unroll
+        for (int s = 0; s < 32; ++s) ddl[s * Sh::NT + threadIdx.x] = T(0);
+    }
     if constexpr (FRC) {
         const ForceDev<T>* fd = fa.dev;
         const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -621,25 +650,36 @@ __device__ __forceinline__ void sweep_tile(const Geom& g, const Fields4<T>& in,
         }
     }
     for (int t0 = 0; t0 < nplanes; t0 += 8) {
-        sweep_step<0, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
-        sweep_step<1, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
-        sweep_step<2, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
-        sweep_step<3, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
-        sweep_step<4, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
-        sweep_step<5, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
-        sweep_step<6, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
-        sweep_step<7, S, PD, LD, NT, VS, P19, RED, FRC>(t0, nplanes, zb, R, X, lds, lds3, g, in,
-                                                      out, w, dv, cf, rk, fa.tab);
+        sweep_step<0, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
+        sweep_step<1, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
+        sweep_step<2, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
+        sweep_step<3, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
+        sweep_step<4, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
+        sweep_step<5, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
+        sweep_step<6, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
+        sweep_step<7, S, PD, LD, NT, VS, P19, RED, FRC, 0, DDL>(
+            t0, nplanes, zb, R, X, lds, lds3, g, in, out, w, dv, cf, rk, fa.tab, (T*)nullptr, (TW*)nullptr, ddl);
     }
     if constexpr (RED) red_store_n<SweepShape<T, TX, TY, LD>::NW>(R.red, R.bad, part);
 }
+
+// Where the x / y first derivatives wait for their output plane: LDS slots
+// for the FP64 array-of-structures register sweeps of at most 256 threads,
+// registers otherwise.  Those kernels need more than 256 registers and run
+// one wave per SIMD; the slots take about 110 registers off the part kept in
+// AGPRs and the copies between the two files.
+#ifndef FD6_DD_LDS
+#define FD6_DD_LDS 1
+#endif
+template <typename T, int TX, int TY, bool LD, int VS>
+constexpr bool kDdInLds = FD6_DD_LDS && sizeof(T) == 8 && TX * TY <= 256 && !LD && VS == 4;
 
 template <typename T, typename TW, int TX, int TY, int S, int PD, bool LD, bool NT, int VS,
           bool FRC>
@@ -647,11 +687,14 @@ __global__ __launch_bounds__(TX* TY)
 void substep55_sweep(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, Coef<T> cf,
                      RKCoef<TW> rk, SweepGrid m, ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
+    constexpr bool DDL = kDdInLds<T, TX, TY, LD, VS>;
     __shared__ T lds[2 * 4 * Sh::FS];
+    __shared__ __attribute__((aligned(16))) T ddl[DDL ? 32 * TX * TY : 2];
     const TileXY t = sweep_tile_of(g, TX, TY, m);
     if (t.zb >= t.ze) return;
-    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, VS, false, false, FRC>(
-        g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa);
+    sweep_tile<T, TW, TX, TY, S, PD, LD, NT, VS, false, false, FRC, DDL>(
+        g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, nullptr, fa,
+        ddl);
 }
 
 // Substeps 1 and 2 of one step in one launch: the temporal blocking the
@@ -753,10 +796,12 @@ void substep55_sweep_red(Geom g, Fields4<T> in, Fields4<T> out, Fields4<TW> w, C
                          RKCoef<TW> rk, SweepGrid m, double* part,
                          ForceArgs<T> fa) {
     using Sh = SweepShape<T, TX, TY, LD>;
+    constexpr bool DDL = kDdInLds<T, TX, TY, LD, VS>;
     __shared__ T lds[2 * 4 * Sh::FS];
+    __shared__ __attribute__((aligned(16))) T ddl[DDL ? 32 * TX * TY : 2];
     const TileXY t = sweep_tile_of(g, TX, TY, m);
-    sweep_tile<T, TW, TX, TY, 3, PD, LD, NT, VS, false, true, FRC>(
-        g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, part, fa);
+    sweep_tile<T, TW, TX, TY, 3, PD, LD, NT, VS, false, true, FRC, DDL>(
+        g, in, out, w, nullptr, cf, rk, t.tx, t.ty, t.zb, t.ze, lds, (lds_t<T>)lds, part, fa, ddl);
 }
 
 // Pass 1 of the 19-point method (Sec. 4.2, Algorithm 3): the same sweep
