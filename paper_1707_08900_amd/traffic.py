@@ -44,10 +44,14 @@ def read_counters(path: str, counter: str):
 
 
 def scale_of(values, expect_kib):
+    """Counter scale from the calibration copy: the largest dispatches of the
+    runtime's copy kernel (the same kernel also serves the program's smaller
+    device copies, which are left out)."""
     copy = [v for k, vs in values.items() if COPY_KERNEL in k for v in vs]
     if not copy:
         raise ValueError("the calibration copy kernel is missing (run with --calibrate-copy)")
-    return expect_kib / statistics.median(copy)
+    top = max(copy)
+    return expect_kib / statistics.median([v for v in copy if v >= 0.9 * top])
 
 
 def summarize(fetch_dir, write_dir, match):
