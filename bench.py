@@ -15,12 +15,12 @@ autotuner.
 
 Beside it, on the same GPU ("forms"): the FP64 and FP32 + FP64-RK3-register
 precision forms, the other layout and the 19-point method at 512^3; the FP32
-step at 256^3, the FP32 and FP64 steps at 128^3 (a state the last-level
-cache holds) and at 768^3 (linear sound wave); the 64-box ensemble in both
-layouts; the forced 19-point 256^3 run.  Every form states its error against
-the FP64 oracle on the same inputs: full fields after one step at 128^3,
-256^3 and 512^3 and for all 64 ensemble boxes, the wave's x-profile against
-the oracle's exact slab replica at 768^3.
+step at 256^3, 384^3 and 640^3, the FP32 and FP64 steps at 128^3 (a state
+the last-level cache holds) and at 768^3 (linear sound wave); the 64-box
+ensemble in both layouts; the forced 19-point 256^3 run.  Every form states
+its error against the FP64 oracle on the same inputs: full fields after one
+step at 128^3 to 640^3 and for all 64 ensemble boxes, the wave's x-profile
+against the oracle's exact slab replica at 768^3.
 
 Prints ONE JSON line (metric, value in grid-point updates/s, roofline of the
 dominant kernel measured with HIP events on its stream, the FP64 oracle's
@@ -567,21 +567,24 @@ def main():
     torch.cuda.empty_cache()
 
     if not a.no_forms and n == 512:
-        # the size sweep: 256^3 (random-phase, full-field error) and 768^3
-        # (the linear sound wave, profile error), FP32 and FP64 at 768^3
-        w256 = si.large_box(256)
-        d256 = [torch.from_numpy(f).cuda() for f in w256.fields]
-        e256, _, out = run_form(torch, fd6, w256, d256, "fp32", "55p", "aos", a.steps, 2,
-                                error_steps=0 if a.no_check else 1)
-        if not a.no_check:
-            o256 = OracleSteps(oracle, si, w256, threads)
-            with_error(e256, out, o256.get("55p", "fp32"))
-        e256["workload"] = "256^3 random-phase |k|<=16 A=0.1, nu=1e-3"
-        forms["fp32_55p_aos_256"] = e256
-        del out, d256
-        log(f"fp32 256^3: {e256['ms_per_step']:.3f} ms/step, "
-            f"{e256['updates_per_s'] / 1e9:.2f} G updates/s, kernel "
-            f"{e256['kernel_hbm_frac']:.3f} of HBM peak")
+        # the size sweep: 256^3, 384^3 and 640^3 (random-phase, full-field
+        # error) and 768^3 (the linear sound wave, profile error), FP32 and
+        # FP64 at 768^3
+        for ns in (256, 384, 640):
+            wn = si.large_box(ns)
+            dn = [torch.from_numpy(f).cuda() for f in wn.fields]
+            en, _, out = run_form(torch, fd6, wn, dn, "fp32", "55p", "aos", a.steps, 2,
+                                  error_steps=0 if a.no_check else 1)
+            del dn
+            if not a.no_check:
+                with_error(en, out, OracleSteps(oracle, si, wn, threads).get("55p", "fp32"))
+            en["workload"] = f"{ns}^3 random-phase |k|<=16 A=0.1, nu=1e-3"
+            forms[f"fp32_55p_aos_{ns}"] = en
+            del out, wn
+            torch.cuda.empty_cache()
+            log(f"fp32 {ns}^3: {en['ms_per_step']:.3f} ms/step, "
+                f"{en['updates_per_s'] / 1e9:.2f} G updates/s, kernel "
+                f"{en['kernel_hbm_frac']:.3f} of HBM peak")
         # 128^3 (16 random-phase modes, |k| <= 8, A = 1e-2, nu = 2e-3): the
         # state of a step (about 100 MB in FP32) stays in the last-level
         # cache between launches, so its fraction is not an HBM figure
