@@ -593,7 +593,7 @@ def main():
         o128 = None if a.no_check else OracleSteps(oracle, si, w128, threads)
         for p128 in ("fp32", "fp64"):
             e128, _, out = run_form(torch, fd6, w128, d128, p128, "55p", "aos", max(a.steps, 100),
-                                    5, error_steps=0 if a.no_check else 1)
+                                    5, graph=True, error_steps=0 if a.no_check else 1)
             if o128 is not None:
                 with_error(e128, out, o128.get("55p", p128))
             e128["workload"] = ("128^3 random-phase |k|<=8 A=1e-2, nu=2e-3 (state held in the "
@@ -601,7 +601,9 @@ def main():
             forms[f"{p128}_55p_aos_128"] = e128
             del out
             log(f"{p128} 128^3: {e128['ms_per_step']:.3f} ms/step, "
-                f"{e128['updates_per_s'] / 1e9:.2f} G updates/s")
+                f"{e128['updates_per_s'] / 1e9:.2f} G updates/s; graph replay "
+                f"{e128['graph_ms_per_step']:.3f} ms/step, "
+                f"{e128['graph_updates_per_s'] / 1e9:.2f} G updates/s")
         del d128
         for sprec in ("fp32", "fp64"):
             e768, _ = sound_form(torch, fd6, oracle, si, 768, sprec, a.steps, 2,
