@@ -268,6 +268,10 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     // this thread's LDS slots instead of registers (slot, field pair, thread)
     using T2 = T __attribute__((ext_vector_type(2)));
     T2* const dd2 = reinterpret_cast<T2*>(ddl);
+    // PIPE: the pinned order of phase (C) below; it pays where one wave runs per
+    // SIMD and the LDS slots left registers for the copies (FP64, the same
+    // kernels as DDL)
+    constexpr bool PIPE = DDL;
     const int t = t0 + PH;
     if (t >= nplanes) return;
     const int p = zb - kR + t;  // plane loaded in this step
@@ -352,6 +356,25 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             R.L[i][sl8(PH - 3)] += T(2) * zs3[i];
             R.L[i][sl8(PH + 3)] = T(-2) * zs3[i];
         }
+    }
+
+    // PIPE: register copies of the fields' x / y windows (the cross and the
+    // diagonals through the column), each filled from LDS one field ahead of
+    // its arithmetic, with the order pinned, so that the LDS latency overlaps
+    // the arithmetic before it (the output plane's for ln rho).  The
+    // operations and their operands are those of the plain order.
+    [[maybe_unused]] T wv[PIPE ? 4 : 1][PIPE ? 7 * W : 1];
+    [[maybe_unused]] auto fill = [&](T* wf, const T* Bf) {
+#pragma unroll
+        for (int dy = -kR; dy <= kR; ++dy)
+#pragma unroll
+            for (int dx = -kR; dx <= kR; ++dx)
+                if (dy == 0 || dx == 0 || dy == dx || dy == -dx)
+                    wf[C0 + dy * W + dx] = Bf[dy * W + dx];
+    };
+    if constexpr (PIPE) {
+        fill(wv[0], B0);
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // (B) finish output plane o = p - 3 before the rest of plane p is formed,
@@ -460,7 +483,6 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
     // (C) the rest of plane p for this column: x / y first derivatives of the
     // four fields (kept 3 planes), the xy part of the linear viscous term, and
     // the k = 1, 2 terms of the xz / yz stencils of outputs p -+ k.
-    // lnrho
     auto dd_put = [&](int f, T dx, T dy) {
         if constexpr (DDL) {
             dd2[(DS * 4 + f) * Sh::NT + threadIdx.x] = T2{dx, dy};
@@ -469,96 +491,206 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
             R.dd[DS][2 * f + 1] = dy;
         }
     };
-    dd_put(0,
-           cf.d1[0][0] * (B0[1] - B0[-1]) + cf.d1[0][1] * (B0[2] - B0[-2]) +
-               cf.d1[0][2] * (B0[3] - B0[-3]),
-           cf.d1[1][0] * (B0[W] - B0[-W]) + cf.d1[1][1] * (B0[2 * W] - B0[-2 * W]) +
-               cf.d1[1][2] * (B0[3 * W] - B0[-3 * W]));
     T lx, ly, lz;  // xy parts of nu (lap u_i + (1/3) d_i div u) at plane p (19-point:
                    // of nu lap u_i)
     T zx[2], zy[2], zz[2];  // scaled k = 1, 2 differences feeding the xz / yz terms
-    // ux
-    {
-        const T c = B1[0];
-        T a[3], b[3];
-        T rx = T(0), ry = T(0), m = T(0);
-#pragma unroll
-        for (int k = 1; k <= 3; ++k) {
-            const T xp = B1[k], xm = B1[-k], yp = B1[k * W], ym = B1[-k * W];
-            a[k - 1] = xp - xm;
-            b[k - 1] = yp - ym;
-            rx += w2[k - 1] * (xp + xm);
-            ry += w2[k - 1] * (yp + ym);
+    if constexpr (PIPE) {
+        // lnrho
+        auto c_lnrho = [&](const T* F) {
+            dd_put(0,
+                   cf.d1[0][0] * (F[1] - F[-1]) + cf.d1[0][1] * (F[2] - F[-2]) +
+                       cf.d1[0][2] * (F[3] - F[-3]),
+                   cf.d1[1][0] * (F[W] - F[-W]) + cf.d1[1][1] * (F[2 * W] - F[-2 * W]) +
+                       cf.d1[1][2] * (F[3 * W] - F[-3 * W]));
+        };
+        // ux
+        auto c_ux = [&](const T* F) {
+            const T c = F[0];
+            T a[3], b[3];
+            T rx = T(0), ry = T(0), m = T(0);
+    #pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                const T xp = F[k], xm = F[-k], yp = F[k * W], ym = F[-k * W];
+                a[k - 1] = xp - xm;
+                b[k - 1] = yp - ym;
+                rx += w2[k - 1] * (xp + xm);
+                ry += w2[k - 1] * (yp + ym);
+                if constexpr (!P19) {
+                    const T t = (F[k * W + k] - F[k * W - k]) + (F[-k * W - k] - F[-k * W + k]);
+                    m += w2[k - 1] * t;
+                }
+            }
+            dd_put(1, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+                   cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
+            if constexpr (P19) {
+                lx = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+                ly = T(0);
+            } else {
+                lx = cf.kxy[0] * c + cf.sg4[0] * rx + cf.sg[1] * ry;  // (4/3) D2x + D2y
+                ly = cf.mu[0] * m;                                     // (1/3) Dxy ux
+            }
             if constexpr (!P19) {
-                const T t = (B1[k * W + k] - B1[k * W - k]) + (B1[-k * W - k] - B1[-k * W + k]);
-                m += w2[k - 1] * t;
+    #pragma unroll
+                for (int k = 0; k < 2; ++k) zz[k] = cf.mu[1] * a[k];  // (1/3) Dxz ux
+            }
+        };
+        // uy
+        auto c_uy = [&](const T* F) {
+            const T c = F[0];
+            T a[3], b[3];
+            T rx = T(0), ry = T(0), m = T(0);
+    #pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                const T xp = F[k], xm = F[-k], yp = F[k * W], ym = F[-k * W];
+                a[k - 1] = xp - xm;
+                b[k - 1] = yp - ym;
+                rx += w2[k - 1] * (xp + xm);
+                ry += w2[k - 1] * (yp + ym);
+                if constexpr (!P19) {
+                    const T t = (F[k * W + k] - F[k * W - k]) + (F[-k * W - k] - F[-k * W + k]);
+                    m += w2[k - 1] * t;
+                }
+            }
+            dd_put(2, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+                   cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
+            if constexpr (P19) {
+                ly = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+            } else {
+                ly += cf.kxy[1] * c + cf.sg[0] * rx + cf.sg4[1] * ry;  // D2x + (4/3) D2y
+                lx += cf.mu[0] * m;                                     // (1/3) Dxy uy
+            }
+            if constexpr (!P19) {
+    #pragma unroll
+                for (int k = 0; k < 2; ++k) zz[k] += cf.mu[2] * b[k];  // (1/3) Dyz uy
+            }
+        };
+        // uz
+        auto c_uz = [&](const T* F) {
+            const T c = F[0];
+            T a[3], b[3];
+            T rx = T(0), ry = T(0);
+    #pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                const T xp = F[k], xm = F[-k], yp = F[k * W], ym = F[-k * W];
+                a[k - 1] = xp - xm;
+                b[k - 1] = yp - ym;
+                rx += w2[k - 1] * (xp + xm);
+                ry += w2[k - 1] * (yp + ym);
+            }
+            dd_put(3, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+                   cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
+            lz = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+            if constexpr (!P19) {
+    #pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    zx[k] = cf.mu[1] * a[k];  // (1/3) Dxz uz
+                    zy[k] = cf.mu[2] * b[k];  // (1/3) Dyz uy
+                }
+            }
+        };
+        __builtin_amdgcn_sched_barrier(0);
+        fill(wv[1], B1);
+        __builtin_amdgcn_sched_barrier(0);
+        c_lnrho(wv[0] + C0);
+        __builtin_amdgcn_sched_barrier(0);
+        fill(wv[2], B2);
+        __builtin_amdgcn_sched_barrier(0);
+        c_ux(wv[1] + C0);
+        __builtin_amdgcn_sched_barrier(0);
+        fill(wv[3], B3);
+        __builtin_amdgcn_sched_barrier(0);
+        c_uy(wv[2] + C0);
+        __builtin_amdgcn_sched_barrier(0);
+        c_uz(wv[3] + C0);
+    } else {
+        dd_put(0,
+               cf.d1[0][0] * (B0[1] - B0[-1]) + cf.d1[0][1] * (B0[2] - B0[-2]) +
+                   cf.d1[0][2] * (B0[3] - B0[-3]),
+               cf.d1[1][0] * (B0[W] - B0[-W]) + cf.d1[1][1] * (B0[2 * W] - B0[-2 * W]) +
+                   cf.d1[1][2] * (B0[3 * W] - B0[-3 * W]));
+        // ux
+        {
+            const T c = B1[0];
+            T a[3], b[3];
+            T rx = T(0), ry = T(0), m = T(0);
+    #pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                const T xp = B1[k], xm = B1[-k], yp = B1[k * W], ym = B1[-k * W];
+                a[k - 1] = xp - xm;
+                b[k - 1] = yp - ym;
+                rx += w2[k - 1] * (xp + xm);
+                ry += w2[k - 1] * (yp + ym);
+                if constexpr (!P19) {
+                    const T t = (B1[k * W + k] - B1[k * W - k]) + (B1[-k * W - k] - B1[-k * W + k]);
+                    m += w2[k - 1] * t;
+                }
+            }
+            dd_put(1, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+                   cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
+            if constexpr (P19) {
+                lx = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+                ly = T(0);
+            } else {
+                lx = cf.kxy[0] * c + cf.sg4[0] * rx + cf.sg[1] * ry;  // (4/3) D2x + D2y
+                ly = cf.mu[0] * m;                                     // (1/3) Dxy ux
+            }
+            if constexpr (!P19) {
+    #pragma unroll
+                for (int k = 0; k < 2; ++k) zz[k] = cf.mu[1] * a[k];  // (1/3) Dxz ux
             }
         }
-        dd_put(1, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
-               cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
-        if constexpr (P19) {
-            lx = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
-            ly = T(0);
-        } else {
-            lx = cf.kxy[0] * c + cf.sg4[0] * rx + cf.sg[1] * ry;  // (4/3) D2x + D2y
-            ly = cf.mu[0] * m;                                     // (1/3) Dxy ux
-        }
-        if constexpr (!P19) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) zz[k] = cf.mu[1] * a[k];  // (1/3) Dxz ux
-        }
-    }
-    // uy
-    {
-        const T c = B2[0];
-        T a[3], b[3];
-        T rx = T(0), ry = T(0), m = T(0);
-#pragma unroll
-        for (int k = 1; k <= 3; ++k) {
-            const T xp = B2[k], xm = B2[-k], yp = B2[k * W], ym = B2[-k * W];
-            a[k - 1] = xp - xm;
-            b[k - 1] = yp - ym;
-            rx += w2[k - 1] * (xp + xm);
-            ry += w2[k - 1] * (yp + ym);
+        // uy
+        {
+            const T c = B2[0];
+            T a[3], b[3];
+            T rx = T(0), ry = T(0), m = T(0);
+    #pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                const T xp = B2[k], xm = B2[-k], yp = B2[k * W], ym = B2[-k * W];
+                a[k - 1] = xp - xm;
+                b[k - 1] = yp - ym;
+                rx += w2[k - 1] * (xp + xm);
+                ry += w2[k - 1] * (yp + ym);
+                if constexpr (!P19) {
+                    const T t = (B2[k * W + k] - B2[k * W - k]) + (B2[-k * W - k] - B2[-k * W + k]);
+                    m += w2[k - 1] * t;
+                }
+            }
+            dd_put(2, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+                   cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
+            if constexpr (P19) {
+                ly = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+            } else {
+                ly += cf.kxy[1] * c + cf.sg[0] * rx + cf.sg4[1] * ry;  // D2x + (4/3) D2y
+                lx += cf.mu[0] * m;                                     // (1/3) Dxy uy
+            }
             if constexpr (!P19) {
-                const T t = (B2[k * W + k] - B2[k * W - k]) + (B2[-k * W - k] - B2[-k * W + k]);
-                m += w2[k - 1] * t;
+    #pragma unroll
+                for (int k = 0; k < 2; ++k) zz[k] += cf.mu[2] * b[k];  // (1/3) Dyz uy
             }
         }
-        dd_put(2, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
-               cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
-        if constexpr (P19) {
-            ly = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
-        } else {
-            ly += cf.kxy[1] * c + cf.sg[0] * rx + cf.sg4[1] * ry;  // D2x + (4/3) D2y
-            lx += cf.mu[0] * m;                                     // (1/3) Dxy uy
-        }
-        if constexpr (!P19) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) zz[k] += cf.mu[2] * b[k];  // (1/3) Dyz uy
-        }
-    }
-    // uz
-    {
-        const T c = B3[0];
-        T a[3], b[3];
-        T rx = T(0), ry = T(0);
-#pragma unroll
-        for (int k = 1; k <= 3; ++k) {
-            const T xp = B3[k], xm = B3[-k], yp = B3[k * W], ym = B3[-k * W];
-            a[k - 1] = xp - xm;
-            b[k - 1] = yp - ym;
-            rx += w2[k - 1] * (xp + xm);
-            ry += w2[k - 1] * (yp + ym);
-        }
-        dd_put(3, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
-               cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
-        lz = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
-        if constexpr (!P19) {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                zx[k] = cf.mu[1] * a[k];  // (1/3) Dxz uz
-                zy[k] = cf.mu[2] * b[k];  // (1/3) Dyz uy
+        // uz
+        {
+            const T c = B3[0];
+            T a[3], b[3];
+            T rx = T(0), ry = T(0);
+    #pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                const T xp = B3[k], xm = B3[-k], yp = B3[k * W], ym = B3[-k * W];
+                a[k - 1] = xp - xm;
+                b[k - 1] = yp - ym;
+                rx += w2[k - 1] * (xp + xm);
+                ry += w2[k - 1] * (yp + ym);
+            }
+            dd_put(3, cf.d1[0][0] * a[0] + cf.d1[0][1] * a[1] + cf.d1[0][2] * a[2],
+                   cf.d1[1][0] * b[0] + cf.d1[1][1] * b[1] + cf.d1[1][2] * b[2]);
+            lz = cf.kp * c + cf.sg[0] * rx + cf.sg[1] * ry;  // D2x + D2y
+            if constexpr (!P19) {
+    #pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    zx[k] = cf.mu[1] * a[k];  // (1/3) Dxz uz
+                    zy[k] = cf.mu[2] * b[k];  // (1/3) Dyz uy
+                }
             }
         }
     }
