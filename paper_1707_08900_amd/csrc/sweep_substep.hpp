@@ -588,17 +588,15 @@ __device__ __forceinline__ void sweep_step(int t0, int nplanes, int zb, SweepReg
                 }
             }
         };
+        // stages: [next window, this field's arithmetic], pinned apart
         __builtin_amdgcn_sched_barrier(0);
         fill(wv[1], B1);
-        __builtin_amdgcn_sched_barrier(0);
         c_lnrho(wv[0] + C0);
         __builtin_amdgcn_sched_barrier(0);
         fill(wv[2], B2);
-        __builtin_amdgcn_sched_barrier(0);
         c_ux(wv[1] + C0);
         __builtin_amdgcn_sched_barrier(0);
         fill(wv[3], B3);
-        __builtin_amdgcn_sched_barrier(0);
         c_uy(wv[2] + C0);
         __builtin_amdgcn_sched_barrier(0);
         c_uz(wv[3] + C0);
