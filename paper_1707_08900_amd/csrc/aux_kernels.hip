@@ -241,10 +241,12 @@ hipError_t launch_export(const Geom& g, const T* src, double* dst, long long zbe
 }
 
 template <typename TW>
-hipError_t launch_export_w(const Geom& g, const TW* src, double* dst, hipStream_t s) {
-    const long long n = (long long)g.nx * g.ny * g.nz;
-    hipLaunchKernelGGL(export_w_kernel<TW>, dim3(grid_for(n, 256)), dim3(256), 0, s, g, src, dst,
-                       n);
+hipError_t launch_export_w(const Geom& g, const TW* src, double* dst, int z0, int nplanes,
+                           hipStream_t s) {
+    // planes [z0, z0 + nplanes) of the compact register, to dst[0 ..)
+    const long long n = (long long)g.nx * g.ny * nplanes;
+    hipLaunchKernelGGL(export_w_kernel<TW>, dim3(grid_for(n, 256)), dim3(256), 0, s, g,
+                       src + (long long)z0 * g.wplane * g.vs, dst, n);
     return hipGetLastError();
 }
 
@@ -327,7 +329,8 @@ hipError_t launch_reduce_final(const double* partials, int nparts, double* resul
                                          hipStream_t);                                     \
     template hipError_t launch_export<T>(const Geom&, const T*, double*, long long, int,    \
                                          hipStream_t);                                     \
-    template hipError_t launch_export_w<T>(const Geom&, const T*, double*, hipStream_t);    \
+    template hipError_t launch_export_w<T>(const Geom&, const T*, double*, int, int,        \
+                                           hipStream_t);                                \
     template hipError_t launch_zero_w<T>(const Geom&, Fields4<T>, hipStream_t);            \
     template hipError_t launch_reduce<T>(const Geom&, Fields4<T>, double*, double*, double, \
                                          hipStream_t);

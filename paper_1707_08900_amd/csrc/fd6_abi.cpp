@@ -547,19 +547,18 @@ int do_rhs(fd6_box* b, double* const out[4]) {
     b->ghosts_ok[b->cur ^ 1] = false;
     if (rc) return rc;
     const Geom& g = b->geom;
-    const long long n = (long long)g.nx * g.ny * g.nz;
+    // export in z-chunks of whole planes that fit the staging area
+    const long long plane_c = (long long)g.nx * g.ny;
+    const int chunk = (int)(b->staging_elems / plane_c);
     for (int q = 0; q < 4; ++q) {
-        // export in chunks that fit the staging area
-        const long long plane_c = (long long)g.nx * g.ny;
-        if (b->staging_elems >= n) {
-            HIPCHK(b, launch_export_w<TW>(g, static_cast<TW*>(b->w[q]), b->staging, b->stream));
-            HIPCHK(b, hipMemcpyAsync(out[q], b->staging, n * sizeof(double),
+        const TW* src = static_cast<const TW*>(b->w[q]);
+        for (int z = 0; z < g.nz; z += chunk) {
+            const int np = (z + chunk <= g.nz) ? chunk : g.nz - z;
+            HIPCHK(b, launch_export_w<TW>(g, src, b->staging, z, np, b->stream));
+            HIPCHK(b, hipMemcpyAsync(out[q] + (long long)z * plane_c, b->staging,
+                                     (size_t)np * plane_c * sizeof(double),
                                      hipMemcpyDeviceToHost, b->stream));
             HIPCHK(b, hipStreamSynchronize(b->stream));
-        } else {
-            (void)plane_c;
-            b->err = "fd6_rhs: box too large for the staging area";
-            return FD6_EUNSUPPORTED;
         }
     }
     return FD6_OK;

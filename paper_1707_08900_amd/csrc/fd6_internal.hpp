@@ -117,7 +117,8 @@ template <typename T>
 hipError_t launch_export(const Geom& g, const T* src, double* dst, long long zbeg, int nplanes,
                          hipStream_t s);
 template <typename TW>
-hipError_t launch_export_w(const Geom& g, const TW* src, double* dst, hipStream_t s);
+hipError_t launch_export_w(const Geom& g, const TW* src, double* dst, int z0, int nplanes,
+                           hipStream_t s);
 template <typename TW>
 hipError_t launch_zero_w(const Geom& g, Fields4<TW> w, hipStream_t s);
 

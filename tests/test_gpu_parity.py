@@ -262,6 +262,23 @@ def test_rhs_hook_fp64(fd6, orc, variant, tile):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("layout", ["soa", "aos"])
+def test_rhs_hook_beyond_the_staging_area(fd6, orc, layout):
+    """The right-hand side of a box larger than the 2^22-value staging area
+    (256 x 128 x 136: chunks of 128 planes and a ragged one of 8) is exported
+    in z-chunks and matches the oracle's at every point."""
+    w = si.fourier_box(0, seed=6, amplitude=0.05, kmax=8.0, shape=(136, 128, 256))
+    box = fd6.Box(w.shape, "fp64", "55p", layout=layout)
+    box.set_params(w.nu, w.cs, w.dx, w.dy, w.dz, w.dt)
+    box.init_fields(w.fields)
+    r = box.rhs()
+    box.close()
+    ref = orc.rhs(w.fields, w.nu, w.cs, w.dx, w.dy, w.dz, "55p")
+    err = rel_err(r, ref)
+    print(f"rhs hook 256x128x136 {layout}: rel err {err:.3e}", flush=True)
+    assert err <= 1e-12
+
+
 def test_reductions_match_oracle(fd6, orc):
     w = si.fourier_box(40, seed=2, amplitude=0.1, kmax=6.0)
     for prec in ("fp64", "fp32"):
