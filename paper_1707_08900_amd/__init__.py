@@ -466,10 +466,14 @@ def reduce_fields_static(fields, dx: float, dy: float, dz: float, out: torch.Ten
     assert ts[0].dim() == 3 and all(t.dtype == dt and t.shape == ts[0].shape for t in ts)
     prec = {torch.float64: PRECISIONS["fp64"], torch.float32: PRECISIONS["fp32"]}[dt]
     assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= 5
+    assert all(t.device == ts[0].device for t in ts) and out.device == ts[0].device
     nz, ny, nx = (int(v) for v in ts[0].shape)
     st = stream if stream is not None else torch.cuda.current_stream(ts[0].device)
-    rc = library().fd6_reduce_fields_static(
-        nx, ny, nz, prec, *[ctypes.c_void_p(t.data_ptr()) for t in ts], float(dx), float(dy),
-        float(dz), ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(out.data_ptr()))
+    # the library takes the static array of the current device
+    with torch.cuda.device(ts[0].device):
+        rc = library().fd6_reduce_fields_static(
+            nx, ny, nz, prec, *[ctypes.c_void_p(t.data_ptr()) for t in ts], float(dx),
+            float(dy), float(dz), ctypes.c_void_p(st.cuda_stream),
+            ctypes.c_void_p(out.data_ptr()))
     if rc != 0:
         raise Fd6Error(rc, "fd6_reduce_fields_static")

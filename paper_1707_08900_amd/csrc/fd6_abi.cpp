@@ -543,9 +543,9 @@ int do_rhs(fd6_box* b, double* const out[4]) {
     int rc = force_sync<T>(b);
     if (rc) return rc;
     rc = do_substep<T, TW>(b, 1, rk);
-    b->cur ^= 1;  // keep the original state current
+    if (rc) return rc;  // a failed substep returns before its in/out swap
+    b->cur ^= 1;        // keep the original state current
     b->ghosts_ok[b->cur ^ 1] = false;
-    if (rc) return rc;
     const Geom& g = b->geom;
     // export in z-chunks of whole planes that fit the staging area
     const long long plane_c = (long long)g.nx * g.ny;
@@ -936,7 +936,10 @@ int build_graphs(fd6_batch* b) {
         int rc = batch_substeps<T, TW>(b, b->cap, p);
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(b->cap, &gr);
-        if (rc) return rc;
+        if (rc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
         if (e != hipSuccess) return hip_fail(b, e, "hipStreamEndCapture");
         b->graph[p] = gr;
         HIPCHK(b, hipGraphInstantiate(&b->exec[p], gr, nullptr, nullptr, 0));
@@ -1661,20 +1664,27 @@ int fd6_batch_tune(fd6_batch* b, const char* cache_path) {
             float best_ms = -1.0f;
             const int old_tile = b->tile, old_zc = b->zchunk;
             int best_tile = old_tile, best_zc = old_zc;
+            // time of one candidate schedule (a warm-up step, which also
+            // captures its graphs, then kBatchTuneSteps timed steps)
+            auto trial = [&](int cand, int zc, float* ms) -> int {
+                int r = build_items<T, TW>(b, cand, zc);
+                if (r == FD6_OK) r = batch_steps<T, TW>(b, 1);
+                if (r) return r;
+                HIPCHK(b, hipEventRecord(ev.a, b->stream));
+                if ((r = batch_steps<T, TW>(b, kBatchTuneSteps)) != FD6_OK) return r;
+                HIPCHK(b, hipEventRecord(ev.b, b->stream));
+                HIPCHK(b, hipEventSynchronize(ev.b));
+                HIPCHK(b, hipEventElapsedTime(ms, ev.a, ev.b));
+                return FD6_OK;
+            };
             int rc = FD6_OK;
             for (int cand = 1; cand < substep55_tile_count() && rc == FD6_OK; ++cand) {
                 int tx, ty;
                 if (substep55_tile_dims(cand, &tx, &ty) != 0) continue;
                 if (b->aos && !substep55_aos_tile_ok(cand)) continue;
                 for (int zc : kBatchTuneChunks) {
-                    if ((rc = build_items<T, TW>(b, cand, zc)) != FD6_OK) break;
-                    if ((rc = batch_steps<T, TW>(b, 1)) != FD6_OK) break;  // warm-up, capture
-                    HIPCHK(b, hipEventRecord(ev.a, b->stream));
-                    if ((rc = batch_steps<T, TW>(b, kBatchTuneSteps)) != FD6_OK) break;
-                    HIPCHK(b, hipEventRecord(ev.b, b->stream));
-                    HIPCHK(b, hipEventSynchronize(ev.b));
                     float ms = 0.0f;
-                    HIPCHK(b, hipEventElapsedTime(&ms, ev.a, ev.b));
+                    if ((rc = trial(cand, zc, &ms)) != FD6_OK) break;
                     if (best_ms < 0.0f || ms < best_ms) best_ms = ms, best_tile = cand, best_zc = zc;
                 }
             }
