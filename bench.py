@@ -279,7 +279,7 @@ def batch_form(torch, fd6, orc, si, steps, threads, layout="aos", schedule=None,
     reinit()
     t0 = time.perf_counter()
     if schedule is None:
-        best = b.tune()  # the library's autotuner (every shape x chunks 0, 32, 48, 64)
+        best = b.tune()  # the library's autotuner (every shape x chunk choice)
     else:
         b.set_schedule(*schedule)
         best = b.get_schedule()
@@ -287,7 +287,7 @@ def batch_form(torch, fd6, orc, si, steps, threads, layout="aos", schedule=None,
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     reinit()
-    b.step(2)
+    b.step(20)  # untimed: the step time settles 10-20 steps after a change of schedule
     torch.cuda.synchronize()
     e0.record(b.stream)
     b.step(steps)

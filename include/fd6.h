@@ -342,27 +342,33 @@ int fd6_batch_init_fields(fd6_batch *batch, int32_t box, const double *lnrho, co
  * sorted longest first and dealt to the workgroups in turn.
  * zchunk = FD6_BATCH_BALANCED: the tile columns of all boxes cut into one run
  * of equal cost per workgroup (a column is split only where a run ends).
+ * zchunk = FD6_BATCH_PACKED: whole tile columns, longest first, each dealt to
+ * the least-loaded workgroup; a column that would take its workgroup past a
+ * target cost (chosen by the library near the mean cost) is split there.
  * Rebuilds the work lists and drops any captured graph.  FD6_EINVAL for a
- * shape out of range, zchunk < 0 other than FD6_BATCH_BALANCED, or
- * 0 < zchunk < 8;
+ * shape out of range, zchunk < 0 other than FD6_BATCH_BALANCED and
+ * FD6_BATCH_PACKED, or 0 < zchunk < 8;
  * FD6_EUNSUPPORTED for a shape the ensemble's layout does not take.  A
  * refused call leaves the schedule in force (and fd6_batch_get_schedule's
  * answer) unchanged.  Default: shape 8 (32 x 8, two planes ahead), chunks of
  * at most 64 planes. */
 #define FD6_BATCH_BALANCED (-1)
+#define FD6_BATCH_PACKED (-2)
 int fd6_batch_set_schedule(fd6_batch *batch, int32_t tile, int32_t zchunk);
 
 /* Autotuner of the ensemble schedule (the shape and chunk choice is the
  * caller's tuning concern, not the method's): times every z-sweep shape the
- * ensemble's layout takes with z-chunk lengths 0 (whole boxes), 32, 48 and 64
- * and with FD6_BATCH_BALANCED -- one warm-up step, then 3 timed steps each,
- * HIP events on the ensemble's
- * stream -- and keeps the fastest.  Advances every box by 4 steps per
- * candidate: call it before the fields of the actual run are set, or set
- * them again afterwards.  cache_path (may be NULL) names a text file of
- * "key tile zchunk" lines, keyed by device name, precision, layout and box
- * shapes: a cached entry is applied without timing, a new result is appended
- * (a file that cannot be opened is ignored).  FD6_ESTATE before parameters
+ * ensemble's layout takes with z-chunk lengths 0 (whole boxes), 32, 48 and 64,
+ * FD6_BATCH_BALANCED and FD6_BATCH_PACKED, in two passes over the candidates
+ * (each trial 10 warm-up steps, since the step time settles only after a
+ * change of schedule, then 8 timed steps, HIP events on the ensemble's
+ * stream; a candidate's time is its faster trial), and keeps the fastest.
+ * Advances every box by 36 steps per candidate: call it before the fields of
+ * the actual run are set, or set them again afterwards.
+ * cache_path (may be NULL) names a text file of "key tile zchunk" lines,
+ * keyed by device name, precision, layout and box shapes: a cached entry is
+ * applied without timing, a new result is appended (a file that cannot be
+ * opened is ignored).  FD6_ESTATE before parameters
  * and fields are set.  If a trial fails, the schedule in force before the
  * call is restored and the failure returned.  Synchronises. */
 int fd6_batch_tune(fd6_batch *batch, const char *cache_path);

@@ -13,10 +13,12 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <functional>
 #include <type_traits>
 #include <algorithm>
 #include <array>
 #include <new>
+#include <queue>
 #include <string>
 #include <utility>
 #include <vector>
@@ -146,11 +148,98 @@ namespace {
 constexpr size_t kAlign = 256;
 // Shortest z chunk of a batch work item (each chunk re-reads 6 planes).
 constexpr int kMinBatchChunk = 8;
-// Schedule value of the z-chunk that selects the balanced partition.
+// Schedule values of the z-chunk that select the balanced partition and the
+// packed deal of whole columns.
 constexpr int kBatchBalanced = -1;
+constexpr int kBatchPacked = -2;
+
+bool batch_zchunk_ok(int zchunk) {
+    return zchunk == kBatchBalanced || zchunk == kBatchPacked || zchunk == 0 ||
+           zchunk >= kMinBatchChunk;
+}
 constexpr long long kMaxFieldElems = (1LL << 31) - 1;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Packed deal of whole tile columns (zb = 0, ze = nz) over G workgroups.  The
+// columns, costed at their planes plus 2 kR for the pipeline refill, are taken
+// longest first, in the given (box, y, x) order among equal lengths, and each
+// goes to the least-loaded workgroup (the lowest index among equals): the first
+// G columns are neighbouring tiles swept at the same time, as in the chunked
+// deal.  A column that would take its workgroup past a target cost is cut
+// where the workgroup reaches it, if both parts keep kMinBatchChunk planes, and
+// its rest is queued again by length.  A cut workgroup holds exactly the target
+// and is never cut again, so at most G columns are split.  Targets from the
+// mean cost to the mean plus the longest column (where nothing is cut any
+// more) are tried, and the deal with the smallest largest load, then the fewest
+// pieces, is kept.  Fills flat with the items of workgroups 0 .. G-1 in turn
+// and first[L] with the offset of workgroup L's list (first[G] = the total).
+void pack_columns(const std::vector<BatchItem>& cols, int G, std::vector<BatchItem>* flat,
+                  std::vector<int>* first) {
+    long long total = 0, longest = 0;
+    for (const BatchItem& c : cols) {
+        const long long k = c.ze - c.zb + 2 * kR;
+        total += k;
+        longest = std::max(longest, k);
+    }
+    struct Piece {
+        int len;
+        long long seq;  // queue order among equal lengths
+        int col, zb;
+    };
+    auto after = [](const Piece& a, const Piece& c) {
+        return a.len != c.len ? a.len < c.len : a.seq > c.seq;
+    };
+    using Load = std::pair<long long, int>;  // (cost so far, workgroup)
+    // Deals every column for one target; returns (largest load, pieces).
+    auto deal = [&](long long target, std::vector<std::vector<BatchItem>>* lists) {
+        std::priority_queue<Piece, std::vector<Piece>, decltype(after)> q(after);
+        for (size_t k = 0; k < cols.size(); ++k)
+            q.push(Piece{cols[k].ze - cols[k].zb, (long long)k, (int)k, cols[k].zb});
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> wg;
+        for (int j = 0; j < G; ++j) wg.push(Load{0, j});
+        long long seq = (long long)cols.size(), largest = 0, npieces = 0;
+        while (!q.empty()) {
+            const Piece p = q.top();
+            q.pop();
+            Load l = wg.top();
+            wg.pop();
+            int take = p.len;
+            const long long fit = target - l.first - 2 * kR;
+            if (l.first + p.len + 2 * kR > target && fit >= kMinBatchChunk &&
+                p.len - fit >= kMinBatchChunk) {
+                take = (int)fit;
+                q.push(Piece{p.len - take, seq++, p.col, p.zb + take});
+            }
+            if (lists) {
+                const BatchItem& c = cols[p.col];
+                (*lists)[l.second].push_back(BatchItem{c.box, c.x0, c.y0, p.zb, p.zb + take});
+            }
+            l.first += take + 2 * kR;
+            largest = std::max(largest, l.first);
+            ++npieces;
+            wg.push(l);
+        }
+        return std::make_pair(largest, npieces);
+    };
+    const long long lo = (total + G - 1) / G;
+    const long long stride = std::max<long long>(1, longest / 64);
+    long long best_target = lo + longest;
+    std::pair<long long, long long> best{-1, 0};
+    for (long long t = lo; t <= lo + longest; t += stride) {
+        const auto m = deal(t, nullptr);
+        if (best.first < 0 || m < best) best = m, best_target = t;
+    }
+    std::vector<std::vector<BatchItem>> lists(G);
+    deal(best_target, &lists);
+    flat->clear();
+    first->assign(G + 1, 0);
+    for (int L = 0; L < G; ++L) {
+        (*first)[L] = (int)flat->size();
+        flat->insert(flat->end(), lists[L].begin(), lists[L].end());
+    }
+    (*first)[G] = (int)flat->size();
+}
 
 struct Plan {
     Geom g;
@@ -777,14 +866,16 @@ int upload_boxes(fd6_batch* b) {
 //    for the pipeline refill); workgroup L sweeps run L, so every workgroup
 //    has the same work, and a column is split only where a run ends (pieces
 //    of at least kMinBatchChunk planes).
+//  * zchunk = kBatchPacked: whole tile columns, longest first, each dealt to
+//    the least-loaded workgroup (pack_columns); only a column that would take
+//    its workgroup past a target cost is split.
 // The batch's schedule, lists and grid change only when the lists are built
 // and uploaded; a refused schedule leaves the previous one in force.
 template <typename T, typename TW>
 int build_items(fd6_batch* b, int tile, int zchunk) {
     int tx = 0, ty = 0;
     if (substep55_tile_dims(tile, &tx, &ty)) return FD6_EINVAL;
-    if (zchunk != kBatchBalanced && (zchunk < 0 || (zchunk > 0 && zchunk < kMinBatchChunk)))
-        return FD6_EINVAL;
+    if (!batch_zchunk_ok(zchunk)) return FD6_EINVAL;
     // persistent grid: every resident workgroup, a multiple of the 8 XCDs
     int dev = 0, cus = 0;
     HIPCHK(b, hipGetDevice(&dev));
@@ -795,7 +886,20 @@ int build_items(fd6_batch* b, int tile, int zchunk) {
     const long long pieces = 8;  // keep G a multiple of the XCD count
     std::vector<BatchItem> flat;
     std::vector<int> first;
-    if (zchunk != kBatchBalanced) {
+    if (zchunk == kBatchPacked) {
+        std::vector<BatchItem> cols;
+        for (int i = 0; i < b->n; ++i) {
+            const Geom& g = b->geom[i];
+            for (int y0 = 0; y0 < g.ny; y0 += ty)
+                for (int x0 = 0; x0 < g.nx; x0 += tx) cols.push_back(BatchItem{i, x0, y0, 0, g.nz});
+        }
+        const long long gsz = resident >= pieces ? resident / pieces * pieces : resident;
+        pack_columns(cols, (int)std::max<long long>(gsz, 1), &flat, &first);
+        if ((long long)flat.size() > b->items_cap) {
+            b->err = "work list larger than the workspace's item capacity";
+            return FD6_EUNSUPPORTED;
+        }
+    } else if (zchunk != kBatchBalanced) {
         std::vector<BatchItem> it;
         std::vector<long long> cost;
         for (int i = 0; i < b->n; ++i) {
@@ -1044,9 +1148,17 @@ int batch_reduce(fd6_batch* b, fd6_reductions* out) {
 
 
 // ---- ensemble autotuner ----------------------------------------------------
-// Candidate z-chunk lengths (0: whole boxes) and timed steps per candidate.
-constexpr int kBatchTuneChunks[] = {0, 32, 48, 64, kBatchBalanced};
-constexpr int kBatchTuneSteps = 3;
+// Candidate z-chunk lengths (0: whole boxes), warm-up and timed steps per
+// trial, and passes over the candidates (a candidate's time is its fastest
+// trial).  After a change of schedule the step time takes 10-20 steps to
+// settle (the first steps of the 64-box ensemble run up to 15% slower), so a
+// trial warms up for 10 steps; the passes interleave the candidates, so a
+// slower clock at one moment does not decide between schedules a few percent
+// apart.
+constexpr int kBatchTuneChunks[] = {0, 32, 48, 64, kBatchBalanced, kBatchPacked};
+constexpr int kBatchTuneWarmup = 10;
+constexpr int kBatchTuneSteps = 8;
+constexpr int kBatchTunePasses = 2;
 
 // Two timing events, destroyed with the scope.
 struct EventPair {
@@ -1605,8 +1717,7 @@ int fd6_batch_init_fields(fd6_batch* b, int32_t box, const double* lnrho, const 
 
 int fd6_batch_set_schedule(fd6_batch* b, int32_t tile, int32_t zchunk) {
     int tx, ty;
-    if (!b || (zchunk != kBatchBalanced && (zchunk < 0 || (zchunk > 0 && zchunk < kMinBatchChunk))) ||
-        substep55_tile_dims(tile, &tx, &ty))
+    if (!b || !batch_zchunk_ok(zchunk) || substep55_tile_dims(tile, &tx, &ty))
         return FD6_EINVAL;
     if (b->aos && !substep55_aos_tile_ok(tile)) return FD6_EUNSUPPORTED;
     return guarded(b, [&]() -> int {
@@ -1664,11 +1775,11 @@ int fd6_batch_tune(fd6_batch* b, const char* cache_path) {
             float best_ms = -1.0f;
             const int old_tile = b->tile, old_zc = b->zchunk;
             int best_tile = old_tile, best_zc = old_zc;
-            // time of one candidate schedule (a warm-up step, which also
-            // captures its graphs, then kBatchTuneSteps timed steps)
+            // time of one candidate schedule (warm-up steps, the first of
+            // which captures its graphs, then kBatchTuneSteps timed steps)
             auto trial = [&](int cand, int zc, float* ms) -> int {
                 int r = build_items<T, TW>(b, cand, zc);
-                if (r == FD6_OK) r = batch_steps<T, TW>(b, 1);
+                if (r == FD6_OK) r = batch_steps<T, TW>(b, kBatchTuneWarmup);
                 if (r) return r;
                 HIPCHK(b, hipEventRecord(ev.a, b->stream));
                 if ((r = batch_steps<T, TW>(b, kBatchTuneSteps)) != FD6_OK) return r;
@@ -1677,17 +1788,24 @@ int fd6_batch_tune(fd6_batch* b, const char* cache_path) {
                 HIPCHK(b, hipEventElapsedTime(ms, ev.a, ev.b));
                 return FD6_OK;
             };
-            int rc = FD6_OK;
-            for (int cand = 1; cand < substep55_tile_count() && rc == FD6_OK; ++cand) {
+            std::vector<std::pair<int, int>> cands;  // (shape, z-chunk)
+            for (int cand = 1; cand < substep55_tile_count(); ++cand) {
                 int tx, ty;
                 if (substep55_tile_dims(cand, &tx, &ty) != 0) continue;
                 if (b->aos && !substep55_aos_tile_ok(cand)) continue;
-                for (int zc : kBatchTuneChunks) {
-                    float ms = 0.0f;
-                    if ((rc = trial(cand, zc, &ms)) != FD6_OK) break;
-                    if (best_ms < 0.0f || ms < best_ms) best_ms = ms, best_tile = cand, best_zc = zc;
-                }
+                for (int zc : kBatchTuneChunks) cands.emplace_back(cand, zc);
             }
+            std::vector<float> fastest(cands.size(), -1.0f);
+            int rc = FD6_OK;
+            for (int pass = 0; pass < kBatchTunePasses && rc == FD6_OK; ++pass)
+                for (size_t k = 0; k < cands.size(); ++k) {
+                    float ms = 0.0f;
+                    if ((rc = trial(cands[k].first, cands[k].second, &ms)) != FD6_OK) break;
+                    if (fastest[k] < 0.0f || ms < fastest[k]) fastest[k] = ms;
+                }
+            for (size_t k = 0; k < cands.size() && rc == FD6_OK; ++k)
+                if (best_ms < 0.0f || fastest[k] < best_ms)
+                    best_ms = fastest[k], best_tile = cands[k].first, best_zc = cands[k].second;
             if (rc != FD6_OK) {
                 // a failed trial leaves the schedule that was in force before
                 (void)build_items<T, TW>(b, old_tile, old_zc);

@@ -179,7 +179,7 @@ def test_batch_validation(pkg):
     try:
         assert lib.fd6_batch_step(h, 1) == -2
         assert lib.fd6_batch_set_schedule(h, 0, 0) == -1
-        assert lib.fd6_batch_set_schedule(h, 1, -2) == -1  # -1 is FD6_BATCH_BALANCED
+        assert lib.fd6_batch_set_schedule(h, 1, -3) == -1  # -1, -2: balanced, packed
         buf = (ctypes.c_double * 8)()
         assert lib.fd6_batch_init_fields(h, 3, buf, buf, buf, buf) == -1
         assert lib.fd6_batch_get_fields(h, 0, buf, buf, buf, buf) == -2

@@ -52,11 +52,12 @@ def run_single(fd6, w, precision, nsteps, tile):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("tile,zchunk", [(3, 0), (1, 8), (4, 0), (8, -1), (1, -1),
-                                         (None, None)])
+@pytest.mark.parametrize("tile,zchunk", [(3, 0), (1, 8), (4, 0), (8, -1), (1, -1), (8, -2),
+                                         (4, -2), (None, None)])
 def test_batch_equals_single_box_runs_bitwise(fd6, precision, tile, zchunk):
     """(None, None): the default schedule, shape 8 with 64-plane chunks;
-    zchunk -1: the balanced partition of the tile columns."""
+    zchunk -1: the balanced partition of the tile columns; -2: the packed deal
+    of whole columns."""
     ws = small_ensemble()
     out, red = run_batch(fd6, ws, precision, 3, tile, zchunk)
     for i, w in enumerate(ws):
@@ -110,7 +111,7 @@ def test_tuner_picks_a_valid_schedule_and_caches_it(fd6, tmp_path):
     for i, w in enumerate(ws):
         b.init_fields(i, w.fields)
     tile, zc = b.tune(cache)
-    assert 1 <= tile < fd6.tile_count() and tile != 9 and zc in (0, 32, 48, 64, -1)
+    assert 1 <= tile < fd6.tile_count() and tile != 9 and zc in (0, 32, 48, 64, -1, -2)
     lines = open(cache).read().split("\n")
     assert len([ln for ln in lines if ln]) == 1 and lines[0].endswith(f" {tile} {zc}")
     b.set_schedule(1, 8)
@@ -136,7 +137,7 @@ def test_refused_schedule_leaves_the_schedule_in_force(fd6):
     for i, w in enumerate(ws):
         b.init_fields(i, w.fields)
     b.set_schedule(6, 16)
-    for tile, zc, status in ((1, 1, -1), (6, 7, -1), (6, -2, -1), (0, 16, -1), (9, 16, -6),
+    for tile, zc, status in ((1, 1, -1), (6, 7, -1), (6, -3, -1), (0, 16, -1), (9, 16, -6),
                              (99, 16, -1)):
         with pytest.raises(fd6.Fd6Error) as ex:
             b.set_schedule(tile, zc)
