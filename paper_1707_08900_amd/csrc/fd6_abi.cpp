@@ -25,6 +25,7 @@
 
 #include "../../include/fd6.h"
 #include "fd6_internal.hpp"
+#include "pack_columns.hpp"
 
 using namespace fd6;
 
@@ -161,85 +162,6 @@ constexpr long long kMaxFieldElems = (1LL << 31) - 1;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Packed deal of whole tile columns (zb = 0, ze = nz) over G workgroups.  The
-// columns, costed at their planes plus 2 kR for the pipeline refill, are taken
-// longest first, in the given (box, y, x) order among equal lengths, and each
-// goes to the least-loaded workgroup (the lowest index among equals): the first
-// G columns are neighbouring tiles swept at the same time, as in the chunked
-// deal.  A column that would take its workgroup past a target cost is cut
-// where the workgroup reaches it, if both parts keep kMinBatchChunk planes, and
-// its rest is queued again by length.  A cut workgroup holds exactly the target
-// and is never cut again, so at most G columns are split.  Targets from the
-// mean cost to the mean plus the longest column (where nothing is cut any
-// more) are tried, and the deal with the smallest largest load, then the fewest
-// pieces, is kept.  Fills flat with the items of workgroups 0 .. G-1 in turn
-// and first[L] with the offset of workgroup L's list (first[G] = the total).
-void pack_columns(const std::vector<BatchItem>& cols, int G, std::vector<BatchItem>* flat,
-                  std::vector<int>* first) {
-    long long total = 0, longest = 0;
-    for (const BatchItem& c : cols) {
-        const long long k = c.ze - c.zb + 2 * kR;
-        total += k;
-        longest = std::max(longest, k);
-    }
-    struct Piece {
-        int len;
-        long long seq;  // queue order among equal lengths
-        int col, zb;
-    };
-    auto after = [](const Piece& a, const Piece& c) {
-        return a.len != c.len ? a.len < c.len : a.seq > c.seq;
-    };
-    using Load = std::pair<long long, int>;  // (cost so far, workgroup)
-    // Deals every column for one target; returns (largest load, pieces).
-    auto deal = [&](long long target, std::vector<std::vector<BatchItem>>* lists) {
-        std::priority_queue<Piece, std::vector<Piece>, decltype(after)> q(after);
-        for (size_t k = 0; k < cols.size(); ++k)
-            q.push(Piece{cols[k].ze - cols[k].zb, (long long)k, (int)k, cols[k].zb});
-        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> wg;
-        for (int j = 0; j < G; ++j) wg.push(Load{0, j});
-        long long seq = (long long)cols.size(), largest = 0, npieces = 0;
-        while (!q.empty()) {
-            const Piece p = q.top();
-            q.pop();
-            Load l = wg.top();
-            wg.pop();
-            int take = p.len;
-            const long long fit = target - l.first - 2 * kR;
-            if (l.first + p.len + 2 * kR > target && fit >= kMinBatchChunk &&
-                p.len - fit >= kMinBatchChunk) {
-                take = (int)fit;
-                q.push(Piece{p.len - take, seq++, p.col, p.zb + take});
-            }
-            if (lists) {
-                const BatchItem& c = cols[p.col];
-                (*lists)[l.second].push_back(BatchItem{c.box, c.x0, c.y0, p.zb, p.zb + take});
-            }
-            l.first += take + 2 * kR;
-            largest = std::max(largest, l.first);
-            ++npieces;
-            wg.push(l);
-        }
-        return std::make_pair(largest, npieces);
-    };
-    const long long lo = (total + G - 1) / G;
-    const long long stride = std::max<long long>(1, longest / 64);
-    long long best_target = lo + longest;
-    std::pair<long long, long long> best{-1, 0};
-    for (long long t = lo; t <= lo + longest; t += stride) {
-        const auto m = deal(t, nullptr);
-        if (best.first < 0 || m < best) best = m, best_target = t;
-    }
-    std::vector<std::vector<BatchItem>> lists(G);
-    deal(best_target, &lists);
-    flat->clear();
-    first->assign(G + 1, 0);
-    for (int L = 0; L < G; ++L) {
-        (*first)[L] = (int)flat->size();
-        flat->insert(flat->end(), lists[L].begin(), lists[L].end());
-    }
-    (*first)[G] = (int)flat->size();
-}
 
 struct Plan {
     Geom g;
@@ -894,7 +816,7 @@ int build_items(fd6_batch* b, int tile, int zchunk) {
                 for (int x0 = 0; x0 < g.nx; x0 += tx) cols.push_back(BatchItem{i, x0, y0, 0, g.nz});
         }
         const long long gsz = resident >= pieces ? resident / pieces * pieces : resident;
-        pack_columns(cols, (int)std::max<long long>(gsz, 1), &flat, &first);
+        pack_columns(cols, (int)std::max<long long>(gsz, 1), 2 * kR, kMinBatchChunk, &flat, &first);
         if ((long long)flat.size() > b->items_cap) {
             b->err = "work list larger than the workspace's item capacity";
             return FD6_EUNSUPPORTED;
