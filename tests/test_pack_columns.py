@@ -51,8 +51,9 @@ def harness(tmp_path_factory):
     d = tmp_path_factory.mktemp("pack")
     src, exe = d / "harness.cpp", d / "harness"
     src.write_text(HARNESS)
-    subprocess.run([cxx, "-O2", "-std=c++17", "-Wall", "-Werror", f"-I{CSRC}", str(src), "-o",
-                    str(exe)], check=True)
+    # container bounds checks on: an index slip in the deal aborts the harness
+    subprocess.run([cxx, "-O2", "-std=c++17", "-Wall", "-Werror", "-D_GLIBCXX_ASSERTIONS",
+                    f"-I{CSRC}", str(src), "-o", str(exe)], check=True)
     return str(exe)
 
 
