@@ -19,6 +19,10 @@ right-hand side must reproduce up to O(h^6):
 * energy: d/dt int (rho u^2/2 + cs^2 rho ln rho) = -2 nu int rho S:S (needs
   the pressure term to match eq. continuity).
 
+Exact to round-off on the periodic grid: the continuity right-hand side sums
+to -sum u . D lnrho (the divergence telescopes), and to zero when lnrho is
+uniform.
+
 Exact symmetries: translation by whole cells (bitwise), axis permutation and
 reflection (round-off), rest state (bitwise).
 """
@@ -227,6 +231,35 @@ def test_mass_momentum_energy_balance(orc, variant):
         # the continuum balance holds up to the O(h^6) truncation error
         assert f_ < 2e-5, residuals
         assert c_ / f_ > 16 or f_ < 1e-12, residuals
+
+
+@pytest.mark.parametrize("variant", ["55p", "19p"])
+def test_continuity_sum_identities_to_round_off(orc, variant):
+    """The exact discrete counterpart of mass conservation.  The continuity
+    right-hand side is -u . D lnrho - D . u (eq. continuity), and every
+    first-derivative stencil of Sec. 2.3 sums to zero over a periodic grid
+    (it telescopes).  So, to round-off:
+    * with uniform lnrho, sum_i r_lnrho = 0 for any velocity field (Sigma
+      lnrho is constant to first order in dt);
+    * in general, sum_i r_lnrho = -sum_i u . D lnrho, with D taken from the
+      independent np.roll formulation.
+    Mass itself, sum exp(lnrho), is not a discrete invariant of the ln rho
+    form: it holds to the O(h^6) truncation error
+    (test_mass_momentum_energy_balance)."""
+    rng = np.random.default_rng(11)
+    shape = (12, 10, 14)
+    h = (0.3, 0.4, 0.5)  # dx, dy, dz
+    u = [rng.normal(scale=0.1, size=shape) for _ in range(3)]
+    r = orc.rhs([np.full(shape, 0.3)] + u, 0.02, 1.0, *h, variant)
+    assert abs(r[0].sum()) < 1e-13 * np.abs(r[0]).sum()
+    lnrho = rng.normal(scale=0.05, size=shape)
+    r = orc.rhs([lnrho] + u, 0.02, 1.0, *h, variant)
+    adv = sum(u[j] * numpy_ref.d1(lnrho, j, h[j]) for j in range(3))
+    tol = 1e-13 * np.abs(r[0]).sum()
+    assert abs(r[0].sum() + adv.sum()) < tol
+    # not satisfied trivially: a planted sign error in the advection term
+    # misses the identity by about 10^9 times the tolerance
+    assert abs(r[0].sum() - adv.sum()) > 1e6 * tol
 
 
 def test_balance_detects_a_planted_sign_error(orc):
