@@ -175,9 +175,10 @@ def test_aos_sound_wave_stays_on_the_closed_form(fd6):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp32_acc64"])
 def test_aos_ensemble_matches_single_boxes(fd6, precision):
-    """Ensemble in the AoS layout (ragged boxes, z-chunked work items): each
-    box equals its single-box run in the default layout bit for bit, and the
-    per-box diagnostics equal the single-box ones."""
+    """Ensemble in the AoS layout (ragged boxes; z-chunked work items, and
+    the packed deal of whole columns cut into pieces): each box equals its
+    single-box run in the default layout bit for bit, and the per-box
+    diagnostics equal the single-box ones."""
     shapes = [(21, 19, 70), (6, 6, 6), (33, 40, 24), (17, 9, 48), (40, 7, 13)]
     ws = [si.noise_box(s, seed=20 + i) for i, s in enumerate(shapes)]
     b = fd6.Batch(shapes, precision, layout="aos")
@@ -187,7 +188,7 @@ def test_aos_ensemble_matches_single_boxes(fd6, precision):
     with pytest.raises(fd6.Fd6Error) as e:
         b.set_schedule(9, 0)
     assert e.value.status == EUNSUPPORTED
-    for tile, zc in ((4, 8), (6, 0)):
+    for tile, zc in ((4, 8), (6, 0), (8, -2)):
         for i, w in enumerate(ws):
             b.init_fields(i, w.fields)
         b.set_schedule(tile, zc)
