@@ -4,6 +4,7 @@ the host compiler and checked for exact coverage of every column, the
 shortest-piece and cut limits, well-formed per-workgroup lists, and a largest
 load no worse than the plain longest-first deal without cuts (computed here
 independently)."""
+import math
 import os
 import random
 import shutil
@@ -142,3 +143,15 @@ def test_more_workgroups_than_columns(harness):
     first, items = run(harness, shapes, 32, 8, 512)
     mk, _, ncut = check(shapes, 32, 8, 512, first, items)
     assert ncut > 0 and mk < lpt_no_cuts(shapes, 32, 8, 512, 6)
+
+
+def test_many_columns_per_workgroup_keep_whole_columns(harness):
+    """When the deal without cuts is already within 0.5% of the mean cost (many
+    columns per workgroup), the packed deal keeps every column whole."""
+    shapes = [(e, e, e) for e in (32 + 16 * (i % 5) for i in range(6000))]
+    ncols = len(columns(shapes, 32, 8))
+    lo = math.ceil(sum(nz + 6 for *_, nz in columns(shapes, 32, 8)) / 512)
+    assert lpt_no_cuts(shapes, 32, 8, 512, 6) * 200 <= lo * 201  # the premise
+    first, items = run(harness, shapes, 32, 8, 512)
+    mk, _, ncut = check(shapes, 32, 8, 512, first, items)
+    assert ncut == 0 and len(items) == ncols and mk <= 1.005 * lo
