@@ -32,6 +32,10 @@ VARIANTS = {"55p": 0, "19p": 1}
 LAYOUTS = {"soa": 0, "aos": 1}  # fd6_desc.flags: 0, FD6_LAYOUT_AOS
 STATUS = {0: "FD6_OK", -1: "FD6_EINVAL", -2: "FD6_ESTATE", -3: "FD6_ENOMEM", -4: "FD6_EHIP",
           -5: "FD6_ENONFINITE", -6: "FD6_EUNSUPPORTED"}
+# z-chunk values of Batch.set_schedule beside chunk lengths (FD6_BATCH_BALANCED,
+# FD6_BATCH_PACKED in include/fd6.h)
+BATCH_BALANCED = -1
+BATCH_PACKED = -2
 
 # every symbol the header declares
 ABI_SYMBOLS = (
@@ -412,6 +416,9 @@ class Batch:
                     "fd6_batch_init_fields")
 
     def set_schedule(self, tile: int, zchunk: int = 0):
+        """Kernel shape and work distribution: zchunk >= 0 (chunks of at most
+        zchunk planes, 0 = whole boxes, dealt in turn), BATCH_BALANCED or
+        BATCH_PACKED."""
         self._check(self.lib.fd6_batch_set_schedule(self.h, tile, zchunk), "fd6_batch_set_schedule")
 
     def get_schedule(self):

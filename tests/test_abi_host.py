@@ -258,3 +258,22 @@ def test_reduce_fields_static_validation(pkg):
                 {"f0": None}, {"f3": None}, {"out": None}, {"dx": 0.0}, {"dy": -1.0},
                 {"dz": float("nan")}, {"dx": float("inf")}):
         assert call(**bad) == -1, bad
+
+
+def test_binding_constants_match_the_header(pkg):
+    """Status codes, precisions, methods, layout flag and the special schedule
+    values of the binding equal the header's definitions."""
+    src = open(HEADER).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(
+        r"#define\s+(FD6_\w+)\s+\(?(-?\d+)\)?", src)}
+    enums = {m.group(1): int(m.group(2)) for m in re.finditer(
+        r"\b(FD6_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+    both = {**enums, **defs}
+    assert pkg.BATCH_BALANCED == both["FD6_BATCH_BALANCED"]
+    assert pkg.BATCH_PACKED == both["FD6_BATCH_PACKED"]
+    for code, name in pkg.STATUS.items():
+        assert both[name] == code, name
+    assert pkg.LAYOUTS["aos"] == both["FD6_LAYOUT_AOS"]
+    assert pkg.PRECISIONS == {"fp64": both["FD6_FP64"], "fp32": both["FD6_FP32"],
+                              "fp32_acc64": both["FD6_FP32_ACC64"]}
+    assert pkg.VARIANTS == {"55p": both["FD6_55P"], "19p": both["FD6_19P"]}
