@@ -13,12 +13,10 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
-#include <functional>
 #include <type_traits>
 #include <algorithm>
 #include <array>
 #include <new>
-#include <queue>
 #include <string>
 #include <utility>
 #include <vector>
@@ -161,7 +159,6 @@ bool batch_zchunk_ok(int zchunk) {
 constexpr long long kMaxFieldElems = (1LL << 31) - 1;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
 
 struct Plan {
     Geom g;
@@ -813,10 +810,12 @@ int build_items(fd6_batch* b, int tile, int zchunk) {
         for (int i = 0; i < b->n; ++i) {
             const Geom& g = b->geom[i];
             for (int y0 = 0; y0 < g.ny; y0 += ty)
-                for (int x0 = 0; x0 < g.nx; x0 += tx) cols.push_back(BatchItem{i, x0, y0, 0, g.nz});
+                for (int x0 = 0; x0 < g.nx; x0 += tx)
+                    cols.push_back(BatchItem{i, x0, y0, 0, g.nz});
         }
         const long long gsz = resident >= pieces ? resident / pieces * pieces : resident;
-        pack_columns(cols, (int)std::max<long long>(gsz, 1), 2 * kR, kMinBatchChunk, &flat, &first);
+        pack_columns(cols, (int)std::max<long long>(gsz, 1), 2 * kR, kMinBatchChunk, &flat,
+                     &first);
         if ((long long)flat.size() > b->items_cap) {
             b->err = "work list larger than the workspace's item capacity";
             return FD6_EUNSUPPORTED;
