@@ -305,6 +305,31 @@ def test_rhs_hook_beyond_the_staging_area(fd6, orc, layout):
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("variant,layout", [("55p", "soa"), ("55p", "aos"), ("19p", "soa")])
+def test_rhs_hook_continuity_sums(fd6, variant, layout):
+    """The GPU's own continuity right-hand side obeys the exact periodic-sum
+    identities of the discrete equations (independently of the oracle's
+    code): the divergence telescopes, so sum r_lnrho = -sum u . D lnrho to
+    round-off (D from the np.roll formulation), and 0 for uniform ln rho."""
+    from oracle import numpy_ref
+    rng = np.random.default_rng(21)
+    shape = (14, 19, 37)
+    h = (0.3, 0.4, 0.5)  # dx, dy, dz
+    u = [rng.normal(scale=0.1, size=shape) for _ in range(3)]
+    lnrho = rng.normal(scale=0.05, size=shape)
+    for lr in (np.full(shape, 0.3), lnrho):
+        box = fd6.Box(shape, "fp64", variant, layout=layout)
+        box.set_params(0.02, 1.0, h[0], h[1], h[2], 0.01)
+        box.init_fields([lr] + u)
+        r0 = box.rhs()[0]
+        box.close()
+        adv = sum(u[j] * numpy_ref.d1(lr, j, h[j]) for j in range(3))
+        tol = 1e-13 * np.abs(r0).sum()
+        assert abs(r0.sum() + adv.sum()) < tol
+    # the identity is not met trivially (a sign error misses it by far)
+    assert abs(r0.sum() - adv.sum()) > 1e6 * tol
+
+
 def test_reductions_match_oracle(fd6, orc):
     w = si.fourier_box(40, seed=2, amplitude=0.1, kmax=6.0)
     for prec in ("fp64", "fp32"):
